@@ -1,0 +1,314 @@
+"""ctypes wrapper around the FP64 CPU oracle (``oracle/*.c``).
+
+THIS IS TEST INFRASTRUCTURE. Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import it. It shares no code with the
+GPU package and imports nothing from it: inputs arrive as plain numpy arrays and
+dictionaries built by the seeded generators.
+
+The oracle follows the paper's Sec. 2.1 (physics), Sec. 2.2.2 (tally) and
+Sec. 3.1 (batch uncertainty); see ``omc_oracle.h`` for the list of pins.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["rng.c", "physics.c", "transport.c"]
+NE = 512
+NA = 512
+MC2 = 0.51099895
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O2, OpenMP, no FMA contraction)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Material(C.Structure):
+    _fields_ = [("n_elem", C.c_int), ("Z", C.POINTER(C.c_int)), ("A", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double)), ("I_eV", C.c_double), ("rho_nom", C.c_double)]
+
+
+class MatTables(C.Structure):
+    _fields_ = [(n, C.c_double * NE) for n in
+                ("muC", "muPE", "muPair", "muTot", "Scol", "Srad", "R", "sigM", "sigB",
+                 "sigHat", "K1")]
+
+
+COUNTER_INT = ["ph_flights", "ph_fictitious", "ph_compton", "ph_photo", "ph_pair", "ph_cutoff",
+               "ph_escaped", "el_steps", "el_hard_cand", "el_hard_fict", "el_moller", "el_brems",
+               "el_absorbed", "el_escaped", "el_boundary", "el_hinge_trunc", "pos_annihil",
+               "push_ph", "push_el", "src_miss"]
+COUNTER_FP = ["E_incident", "E_deposited", "E_escaped", "E_pair_rest", "E_annih_rest"]
+
+
+class Counters(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in COUNTER_INT] + [(n, C.c_double) for n in COUNTER_FP]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n in COUNTER_INT + COUNTER_FP}
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("density", C.POINTER(C.c_float)), ("mat", C.POINTER(C.c_uint8)),
+                ("n_mats", C.c_int), ("mats", C.POINTER(Material)),
+                ("particle", C.c_int), ("n_bins", C.c_int),
+                ("edges", C.POINTER(C.c_double)), ("weights", C.POINTER(C.c_double)),
+                ("mono_E", C.c_double), ("geometry", C.c_int),
+                ("ssd", C.c_double), ("z_field", C.c_double),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("sx", C.c_double), ("sy", C.c_double),
+                ("gantry_deg", C.c_double), ("iso_x", C.c_double), ("iso_z", C.c_double),
+                ("Eabs_e", C.c_double), ("Eabs_g", C.c_double), ("Wcc", C.c_double),
+                ("kc", C.c_double), ("dmax_s", C.c_double), ("f_E", C.c_double),
+                ("n_batches", C.c_int), ("kerma_mode", C.c_int), ("csda_mode", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        up = C.POINTER(C.c_uint32)
+        L.orc_philox4x32_10.argtypes = [up, up, up]
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_stream_words.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32,
+                                       C.c_uint32, up]
+        for name in ("orc_sigma_kn",):
+            getattr(L, name).argtypes = [C.c_double]
+            getattr(L, name).restype = C.c_double
+        for name in ("orc_sigma_pe_atom", "orc_sigma_pair_atom"):
+            getattr(L, name).argtypes = [C.c_int, C.c_double]
+            getattr(L, name).restype = C.c_double
+        L.orc_inv_X0_element.argtypes = [C.c_int, C.c_double]
+        L.orc_inv_X0_element.restype = C.c_double
+        L.orc_material_inv_X0.argtypes = [C.POINTER(Material)]
+        L.orc_material_inv_X0.restype = C.c_double
+        for name in ("orc_scol_restricted", "orc_srad_restricted", "orc_sigma_moller",
+                     "orc_sigma_brems"):
+            getattr(L, name).argtypes = [C.POINTER(Material), C.c_double, C.c_double]
+            getattr(L, name).restype = C.c_double
+        L.orc_K1.argtypes = [C.POINTER(Material), C.c_double]
+        L.orc_K1.restype = C.c_double
+        L.orc_ms_m1.argtypes = [C.c_double]
+        L.orc_ms_m1.restype = C.c_double
+        L.orc_node_energy.argtypes = [C.c_int]
+        L.orc_node_energy.restype = C.c_double
+        L.orc_build_material.argtypes = [C.POINTER(Material), C.c_double, C.c_double,
+                                         C.POINTER(MatTables)]
+        L.orc_build_ms_table.argtypes = [dp]
+        L.orc_table_lookup.argtypes = [dp, C.c_double]
+        L.orc_table_lookup.restype = C.c_double
+        L.orc_range_inverse.argtypes = [dp, C.c_double]
+        L.orc_range_inverse.restype = C.c_double
+        L.orc_ms_screening.argtypes = [dp, C.c_double]
+        L.orc_ms_screening.restype = C.c_double
+        L.orc_sample_compton.argtypes = [C.c_double, C.c_uint32, C.c_uint32, dp, dp, up]
+        L.orc_sample_moller.argtypes = [C.c_double, C.c_double, C.c_uint32, C.c_uint32, dp]
+        L.orc_sample_brems.argtypes = [C.c_double, C.c_double, C.c_uint32, C.c_uint32, dp]
+        L.orc_sample_ms.argtypes = [dp, C.c_double, C.c_uint32, C.c_uint32, dp]
+        L.orc_rotate.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_sample_source.argtypes = [C.POINTER(Problem), C.c_uint32, C.c_uint32, C.c_uint32,
+                                        dp, dp, dp]
+        L.orc_first_interaction.argtypes = [C.POINTER(Problem), C.c_uint32, C.c_uint32,
+                                            C.c_uint32, dp, C.POINTER(C.c_int),
+                                            C.POINTER(C.c_uint64)]
+        L.orc_first_interaction.restype = C.c_int
+        L.orc_run.argtypes = [C.POINTER(Problem), C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
+                              dp, dp, C.POINTER(Counters)]
+        L.orc_run.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _uptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint32))
+
+
+# --- random numbers ----------------------------------------------------------------
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_uptr(c), _uptr(k), _uptr(out))
+    return out
+
+
+def u01(x):
+    return lib().orc_u01(int(x))
+
+
+def stream_words(seed, h, q, n0, nblocks):
+    out = np.zeros(4 * nblocks, dtype=np.uint32)
+    lib().orc_stream_words(seed, h, q, n0, nblocks, _uptr(out))
+    return out
+
+
+# --- materials and tables -------------------------------------------------------------
+
+class _MatHolder:
+    """Keeps the numpy buffers behind a ctypes Material alive."""
+
+    def __init__(self, spec):
+        self.Z = np.ascontiguousarray(spec["Z"], dtype=np.int32)
+        self.A = np.ascontiguousarray(spec["A"], dtype=np.float64)
+        self.w = np.ascontiguousarray(spec["w"], dtype=np.float64)
+        self.struct = Material(len(self.Z), self.Z.ctypes.data_as(C.POINTER(C.c_int)),
+                               _dptr(self.A), _dptr(self.w), float(spec["I_eV"]),
+                               float(spec["rho_nom"]))
+
+
+def material(spec):
+    return _MatHolder(spec)
+
+
+def mat_tables(spec, Wcc=0.05, kc=0.2):
+    h = _MatHolder(spec)
+    t = MatTables()
+    lib().orc_build_material(C.byref(h.struct), Wcc, kc, C.byref(t))
+    return {n: np.array(getattr(t, n)) for n, _ in MatTables._fields_}
+
+
+def ms_table():
+    out = np.zeros(NA)
+    lib().orc_build_ms_table(_dptr(out))
+    return out
+
+
+def node_energies():
+    return np.array([lib().orc_node_energy(i) for i in range(NE)])
+
+
+# --- problems ------------------------------------------------------------------------------
+
+DEFAULT_PARAMS = dict(Eabs_e=0.2, Eabs_g=0.05, Wcc=0.05, kc=0.2, dmax_s=0.5, f_E=0.25,
+                      n_batches=10, kerma_mode=0, csda_mode=0)
+
+
+class _ProblemHolder:
+    def __init__(self, phantom, source, params):
+        p = dict(DEFAULT_PARAMS)
+        p.update(params or {})
+        self.density = np.ascontiguousarray(phantom["density"], dtype=np.float32).ravel(order="C")
+        self.mat = np.ascontiguousarray(phantom["material"], dtype=np.uint8).ravel(order="C")
+        self.mholders = [_MatHolder(m) for m in phantom["materials"]]
+        self.mats = (Material * len(self.mholders))(*[h.struct for h in self.mholders])
+        nb = int(source.get("n_bins", 0) or 0)
+        self.edges = np.ascontiguousarray(source.get("edges", np.zeros(1)), dtype=np.float64)
+        self.weights = np.ascontiguousarray(source.get("weights", np.zeros(1)), dtype=np.float64)
+        nz, ny, nx = phantom["shape"]
+        dz, dy, dx = phantom["voxel"]
+        self.struct = Problem(
+            nx, ny, nz, dx, dy, dz,
+            self.density.ctypes.data_as(C.POINTER(C.c_float)),
+            self.mat.ctypes.data_as(C.POINTER(C.c_uint8)),
+            len(self.mholders), self.mats,
+            int(source["particle"]), nb, _dptr(self.edges), _dptr(self.weights),
+            float(source.get("mono_E", 0.0)), int(source["geometry"]),
+            float(source.get("ssd", 100.0)), float(source.get("z_field", 0.0)),
+            float(source["fx"]), float(source["fy"]), float(source["cx"]), float(source["cy"]),
+            float(source.get("sx", source["cx"])), float(source.get("sy", source["cy"])),
+            float(source.get("gantry_deg", 0.0)), float(source.get("iso_x", 0.0)),
+            float(source.get("iso_z", 0.0)),
+            p["Eabs_e"], p["Eabs_g"], p["Wcc"], p["kc"], p["dmax_s"], p["f_E"],
+            int(p["n_batches"]), int(p["kerma_mode"]), int(p["csda_mode"]))
+
+
+def run(phantom, source, n, seed=1, h0=0, params=None, threads=None):
+    """Transport histories h0..h0+n-1. Returns (dose, dose2, counters) with dose
+    shaped like the phantom (z, y, x), MeV/g per history."""
+    pr = _ProblemHolder(phantom, source, params)
+    nvox = pr.density.size
+    dose = np.zeros(nvox)
+    dose2 = np.zeros(nvox)
+    cnt = Counters()
+    nt = threads if threads else min(16, os.cpu_count() or 1)
+    rc = lib().orc_run(C.byref(pr.struct), int(n), int(seed), int(h0), int(nt), _dptr(dose),
+                       _dptr(dose2), C.byref(cnt))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem (rc=%d)" % rc)
+    shape = tuple(phantom["shape"])
+    return dose.reshape(shape), dose2.reshape(shape), cnt.as_dict()
+
+
+def first_interaction(phantom, source, n, seed=1, h0=0, params=None):
+    pr = _ProblemHolder(phantom, source, params)
+    pos = np.zeros(3 * n)
+    typ = np.zeros(n, dtype=np.int32)
+    nf = C.c_uint64(0)
+    rc = lib().orc_first_interaction(C.byref(pr.struct), seed, h0, n, _dptr(pos),
+                                     typ.ctypes.data_as(C.POINTER(C.c_int)), C.byref(nf))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    return pos.reshape(n, 3), typ, nf.value
+
+
+def sample_source(phantom, source, n, seed=1, h0=0):
+    pr = _ProblemHolder(phantom, source, None)
+    E = np.zeros(n)
+    x = np.zeros(3 * n)
+    d = np.zeros(3 * n)
+    lib().orc_sample_source(C.byref(pr.struct), seed, h0, n, _dptr(E), _dptr(x), _dptr(d))
+    return E, x.reshape(n, 3), d.reshape(n, 3)
+
+
+def sample_compton(E, n, seed=1):
+    eps = np.zeros(n)
+    cost = np.zeros(n)
+    words = np.zeros(n, dtype=np.uint32)
+    lib().orc_sample_compton(E, seed, n, _dptr(eps), _dptr(cost), _uptr(words))
+    return eps, cost, words
+
+
+def sample_moller(T, Wcc, n, seed=1):
+    out = np.zeros(n)
+    lib().orc_sample_moller(T, Wcc, seed, n, _dptr(out))
+    return out
+
+
+def sample_brems(T, kc, n, seed=1):
+    out = np.zeros(n)
+    lib().orc_sample_brems(T, kc, seed, n, _dptr(out))
+    return out
+
+
+def sample_ms(x, n, seed=1):
+    tab = ms_table()
+    out = np.zeros(n)
+    lib().orc_sample_ms(_dptr(tab), x, seed, n, _dptr(out))
+    return out
+
+
+def rotate(d, cost, sint, cphi, sphi):
+    v = np.ascontiguousarray(d, dtype=np.float64).copy()
+    lib().orc_rotate(_dptr(v), cost, sint, cphi, sphi)
+    return v
+
+
+def fn(name):
+    """Direct access to a closed-form function of the oracle library."""
+    return getattr(lib(), name)

@@ -1,0 +1,904 @@
+/*
+ * transport.c -- oracle coupled photon-electron transport. Test infrastructure
+ * only (see omc_oracle.h): the GPU product path never calls this code.
+ *
+ * One history at a time, last-in-first-out over its particles (Sec. 2.2.1,
+ * Table 1 describes the GPU scheduling; the physics of a particle does not
+ * depend on the order because each particle owns its random stream).
+ *
+ *   photons   Sec. 2.1: Woodcock flights with the phantom majorant, real-event
+ *             test, Compton (Klein-Nishina, Butcher-Messel sampling),
+ *             photoelectric (local absorption), pair (e-/e+ along the photon,
+ *             kinetic energy split uniformly).
+ *   electrons Sec. 2.1: Class II condensed history; step
+ *             d = min(d_vox, d_maxs, d_maxe, d_abs, d_event); random hinge with
+ *             the multiple-scattering deflection; CSDA loss from the range table
+ *             deposited in the voxel of the step; hard event accepted with the
+ *             Woodcock ratio; Moller or bremsstrahlung; positrons annihilate
+ *             into two back-to-back photons at the end of the track.
+ *   tally     Sec. 2.2.2 (atomic dose counter) and Sec. 3.1 (sigma_D): energy
+ *             per voxel per batch of histories, folded to dose (MeV/g per
+ *             history) and the sum of squared batch doses.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+#include "omc_oracle.h"
+#include "internal.h"
+
+#define MC2 0.51099895
+#define PI 3.14159265358979323846
+
+enum { LIM_VOX = 0, LIM_MAXS, LIM_MAXE, LIM_ABS, LIM_EVENT };
+enum { PT_PHOTON = 0, PT_ELECTRON = 1, PT_POSITRON = 2 };
+
+/* --- per-particle random stream --------------------------------------------- */
+typedef struct {
+    uint32_t key[2];
+    uint64_t q;
+    uint32_t n;  /* next block */
+    int nw;      /* words of the cached block already used (4 = empty) */
+    uint32_t w[4];
+} rng_t;
+
+static void rng_init(rng_t* r, uint32_t seed, uint32_t h, uint64_t q, uint32_t n0)
+{
+    r->key[0] = seed;
+    r->key[1] = h;
+    r->q = q;
+    r->n = n0;
+    r->nw = 4;
+}
+
+static uint32_t rng_word(rng_t* r)
+{
+    if (r->nw == 4) {
+        const uint32_t ctr[4] = {r->n, (uint32_t)r->q, (uint32_t)(r->q >> 32), 0u};
+        orc_philox4x32_10(ctr, r->key, r->w);
+        r->n += 1;
+        r->nw = 0;
+    }
+    return r->w[r->nw++];
+}
+
+static double rng_u(rng_t* r) { return orc_u01(rng_word(r)); }
+
+/* A child's particle id: two raw words of the parent's stream, the high bit
+ * set so that no child shares the source particle's id 0. */
+static uint64_t rng_child_id(rng_t* r)
+{
+    const uint32_t lo = rng_word(r);
+    const uint32_t hi = rng_word(r);
+    return ((uint64_t)(hi | 0x80000000u) << 32) | (uint64_t)lo;
+}
+
+/* --- particles and the per-history stack ----------------------------------------- */
+typedef struct {
+    int type;
+    double E;
+    double x[3], d[3];
+    int iv[3];
+    double nmfp; /* remaining mean free paths to the next hard event; <0 unset */
+    rng_t rng;
+} part_t;
+
+typedef struct {
+    part_t* a;
+    size_t n, cap;
+} stack_t;
+
+static void stack_push(stack_t* s, const part_t* p)
+{
+    if (s->n == s->cap) {
+        s->cap = s->cap ? 2 * s->cap : 64;
+        s->a = (part_t*)realloc(s->a, s->cap * sizeof(part_t));
+    }
+    s->a[s->n++] = *p;
+}
+
+/* --- run context ------------------------------------------------------------- */
+typedef struct {
+    const orc_problem* P;
+    uint32_t seed;
+    int n[3];
+    double h[3];
+    size_t nvox;
+    double* rho;
+    orc_mat_tables* tab;
+    double* Rabs;  /* range at the electron absorption energy, per material */
+    double muhat[ORC_NE];
+    double log2A[ORC_NA];
+    double* cdf;
+} ctx_t;
+
+typedef struct {
+    double* grid;
+    orc_counters c;
+} tally_t;
+
+static size_t lin(const ctx_t* C, const int iv[3])
+{
+    return (size_t)iv[0] + (size_t)C->n[0] * ((size_t)iv[1] + (size_t)C->n[1] * (size_t)iv[2]);
+}
+
+static void deposit(tally_t* t, size_t v, double e)
+{
+    t->grid[v] += e;
+    t->c.E_deposited += e;
+}
+
+static double lerp(const double* y, int i, double f) { return y[i] + f * (y[i + 1] - y[i]); }
+
+/* Voxel containing x; 0 if outside the box. */
+static int locate(const ctx_t* C, const double x[3], int iv[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const double fl = floor(x[a] / C->h[a]);
+        if (fl < 0.0 || fl >= (double)C->n[a]) return 0;
+        iv[a] = (int)fl;
+    }
+    return 1;
+}
+
+/* Distance along d to the nearest face of voxel iv; ties go to the lower axis. */
+static double dist_to_face(const ctx_t* C, const int iv[3], const double x[3], const double d[3],
+                           int* axis)
+{
+    double best = INFINITY;
+    int ax = 0;
+    for (int a = 0; a < 3; ++a) {
+        double s;
+        if (d[a] > 0.0) s = ((double)(iv[a] + 1) * C->h[a] - x[a]) / d[a];
+        else if (d[a] < 0.0) s = ((double)iv[a] * C->h[a] - x[a]) / d[a];
+        else continue;
+        if (s < best) {
+            best = s;
+            ax = a;
+        }
+    }
+    if (best < 0.0) best = 0.0;
+    *axis = ax;
+    return best;
+}
+
+void orc_rotate(double d[3], double cost, double sint, double cphi, double sphi)
+{
+    const double u = d[0], v = d[1], w = d[2];
+    const double r2 = 1.0 - w * w;
+    if (r2 < 1e-12) {
+        d[0] = sint * cphi;
+        d[1] = sint * sphi;
+        d[2] = w >= 0.0 ? cost : -cost;
+        return;
+    }
+    const double r = sqrt(r2);
+    d[0] = u * cost + sint * (u * w * cphi - v * sphi) / r;
+    d[1] = v * cost + sint * (v * w * cphi + u * sphi) / r;
+    d[2] = w * cost - sint * cphi * r;
+}
+
+/* --- samplers ------------------------------------------------------------------ */
+
+/* Klein-Nishina by Butcher and Messel: eps = E'/E is drawn from the mixture of
+ * 1/eps (weight a1) and eps (weight a2) on [eps0, 1] and accepted with
+ * g = 1 - eps sin^2/(1 + eps^2). Returns eps, sets t = 1 - cos(theta). */
+static double sample_compton_eps(rng_t* r, double k, double* t_out)
+{
+    const double e0 = 1.0 / (1.0 + 2.0 * k);
+    const double a1 = log(1.0 + 2.0 * k);
+    const double a2 = 0.5 * (1.0 - e0 * e0);
+    for (;;) {
+        const double ua = rng_u(r), ub = rng_u(r), uc = rng_u(r);
+        double eps;
+        if (ua * (a1 + a2) < a1) eps = exp(-a1 * ub);
+        else eps = sqrt(e0 * e0 + (1.0 - e0 * e0) * ub);
+        const double t = (1.0 - eps) / (k * eps);
+        const double sin2 = t * (2.0 - t);
+        if (uc <= 1.0 - eps * sin2 / (1.0 + eps * eps)) {
+            *t_out = t;
+            return eps;
+        }
+    }
+}
+
+/* Moller: eps = W/T from 1/eps^2 on [eps0, 1/2], accepted with the rest of
+ * the cross section times eps^2, bounded by 2 + a^2/4. */
+static double sample_moller_eps(rng_t* r, double T, double Wcc)
+{
+    const double e0 = Wcc / T;
+    const double tau = T / MC2;
+    const double g = tau + 1.0;
+    const double a = tau / g;
+    const double b = (2.0 * tau + 1.0) / (g * g);
+    for (;;) {
+        const double ua = rng_u(r), ub = rng_u(r);
+        const double eps = e0 / (1.0 - ua * (1.0 - 2.0 * e0));
+        const double rr = eps / (1.0 - eps);
+        if (ub * (2.0 + 0.25 * a * a) <= 1.0 + rr * rr + a * a * eps * eps - b * rr) return eps;
+    }
+}
+
+/* Bremsstrahlung: k from 1/k on [kc, T], accepted with 1 - y + 0.75 y^2. */
+static double sample_brems_k(rng_t* r, double T, double kc)
+{
+    const double lr = log(T / kc);
+    for (;;) {
+        const double ua = rng_u(r), ub = rng_u(r);
+        const double k = kc * exp(ua * lr);
+        const double y = k / T;
+        if (ub <= 1.0 - y + 0.75 * y * y) return k;
+    }
+}
+
+/* Screened-Rutherford deflection with screening A: 1 - cos = 2 A u/(1 + A - u). */
+static double sample_ms(rng_t* r, double A)
+{
+    const double u = rng_u(r);
+    return 2.0 * A * u / (1.0 + A - u);
+}
+
+/* --- secondaries ------------------------------------------------------------------ */
+static void emit_photon(const ctx_t* C, stack_t* st, tally_t* t, rng_t* parent, double E,
+                        const double x[3], const int iv[3], const double d[3]);
+
+static void annihilate(const ctx_t* C, stack_t* st, tally_t* t, rng_t* r, const double x[3],
+                       const int iv[3])
+{
+    t->c.pos_annihil++;
+    t->c.E_annih_rest += 2.0 * MC2;
+    const double c = 2.0 * rng_u(r) - 1.0;
+    const double phi = 2.0 * PI * rng_u(r);
+    const double s = sqrt((1.0 - c) * (1.0 + c));
+    const double a[3] = {s * cos(phi), s * sin(phi), c};
+    const double b[3] = {-a[0], -a[1], -a[2]};
+    emit_photon(C, st, t, r, MC2, x, iv, a);
+    emit_photon(C, st, t, r, MC2, x, iv, b);
+}
+
+static void emit_photon(const ctx_t* C, stack_t* st, tally_t* t, rng_t* parent, double E,
+                        const double x[3], const int iv[3], const double d[3])
+{
+    if (E >= C->P->Eabs_g) {
+        part_t c;
+        c.type = PT_PHOTON;
+        c.E = E;
+        memcpy(c.x, x, sizeof c.x);
+        memcpy(c.d, d, sizeof c.d);
+        memcpy(c.iv, iv, sizeof c.iv);
+        c.nmfp = -1.0;
+        rng_init(&c.rng, C->seed, parent->key[1], rng_child_id(parent), 0u);
+        stack_push(st, &c);
+        t->c.push_ph++;
+    } else {
+        deposit(t, lin(C, iv), E);
+    }
+}
+
+static void emit_electron(const ctx_t* C, stack_t* st, tally_t* t, rng_t* parent, int type,
+                          double E, const double x[3], const int iv[3], const double d[3])
+{
+    if (!C->P->kerma_mode && E >= C->P->Eabs_e) {
+        part_t c;
+        c.type = type;
+        c.E = E;
+        memcpy(c.x, x, sizeof c.x);
+        memcpy(c.d, d, sizeof c.d);
+        memcpy(c.iv, iv, sizeof c.iv);
+        c.nmfp = -1.0;
+        rng_init(&c.rng, C->seed, parent->key[1], rng_child_id(parent), 0u);
+        stack_push(st, &c);
+        t->c.push_el++;
+    } else {
+        deposit(t, lin(C, iv), E);
+        if (type == PT_POSITRON) annihilate(C, st, t, parent, x, iv);
+    }
+}
+
+/* --- photons ----------------------------------------------------------------------- */
+
+/* Woodcock flights until a real interaction; 0 if the photon left the box. */
+static int woodcock(const ctx_t* C, part_t* p, tally_t* t, size_t* vout, int* iout, double* fout)
+{
+    int i;
+    double f;
+    orc__grid_pos(p->E, &i, &f);
+    const double mh = lerp(C->muhat, i, f);
+    for (;;) {
+        const double s = -log(rng_u(&p->rng)) / mh;
+        for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + s * p->d[a];
+        t->c.ph_flights++;
+        if (!locate(C, p->x, p->iv)) {
+            t->c.E_escaped += p->E;
+            t->c.ph_escaped++;
+            return 0;
+        }
+        const size_t v = lin(C, p->iv);
+        const orc_mat_tables* T = &C->tab[C->P->mat[v]];
+        const double mt = lerp(T->muTot, i, f);
+        if (rng_u(&p->rng) * mh < C->rho[v] * mt) {
+            *vout = v;
+            *iout = i;
+            *fout = f;
+            return 1;
+        }
+        t->c.ph_fictitious++;
+    }
+}
+
+/* Interaction type at a real event: 1 Compton, 2 photoelectric, 3 pair.
+ * Below the pair threshold the pair interval counts as absorption. */
+static int select_type(const ctx_t* C, part_t* p, size_t v, int i, double f)
+{
+    const orc_mat_tables* T = &C->tab[C->P->mat[v]];
+    const double mt = lerp(T->muTot, i, f);
+    const double sel = rng_u(&p->rng) * mt;
+    const double mc = lerp(T->muC, i, f);
+    const double mp = lerp(T->muPE, i, f);
+    if (sel < mc) return 1;
+    if (sel < mc + mp) return 2;
+    if (p->E <= 2.0 * MC2) return 2;
+    return 3;
+}
+
+static void compton(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
+{
+    const double E = p->E;
+    const double k = E / MC2;
+    double tt;
+    const double eps = sample_compton_eps(&p->rng, k, &tt);
+    const double sin2 = tt * (2.0 - tt);
+    const double cost = 1.0 - tt;
+    const double sint = sqrt(sin2 > 0.0 ? sin2 : 0.0);
+    const double phi = 2.0 * PI * rng_u(&p->rng);
+    const double d0[3] = {p->d[0], p->d[1], p->d[2]};
+    orc_rotate(p->d, cost, sint, cos(phi), sin(phi));
+    const double Ep = eps * E;
+    const double Te = E - Ep;
+    /* recoil electron: momentum balance E d0 = E' d + p_e */
+    double pe[3];
+    for (int a = 0; a < 3; ++a) pe[a] = E * d0[a] - Ep * p->d[a];
+    const double nrm = sqrt(pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2]);
+    double de[3];
+    for (int a = 0; a < 3; ++a) de[a] = nrm > 0.0 ? pe[a] / nrm : d0[a];
+    t->c.ph_compton++;
+    emit_electron(C, st, t, &p->rng, PT_ELECTRON, Te, p->x, p->iv, de);
+    p->E = Ep;
+}
+
+static void pair(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
+{
+    const double K = p->E - 2.0 * MC2;
+    const double Tm = rng_u(&p->rng) * K;
+    const double Tp = K - Tm;
+    t->c.ph_pair++;
+    t->c.E_pair_rest += 2.0 * MC2;
+    emit_electron(C, st, t, &p->rng, PT_ELECTRON, Tm, p->x, p->iv, p->d);
+    emit_electron(C, st, t, &p->rng, PT_POSITRON, Tp, p->x, p->iv, p->d);
+}
+
+static void transport_photon(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
+{
+    for (;;) {
+        if (p->E < C->P->Eabs_g) {
+            deposit(t, lin(C, p->iv), p->E);
+            t->c.ph_cutoff++;
+            return;
+        }
+        size_t v;
+        int i;
+        double f;
+        if (!woodcock(C, p, t, &v, &i, &f)) return;
+        const int type = select_type(C, p, v, i, f);
+        if (type == 1) {
+            compton(C, p, st, t);
+        } else if (type == 2) {
+            deposit(t, v, p->E);
+            t->c.ph_photo++;
+            return;
+        } else {
+            pair(C, p, st, t);
+            return;
+        }
+    }
+}
+
+/* --- electrons and positrons -------------------------------------------------------- */
+
+static void moller(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
+{
+    const double T = p->E;
+    if (T <= 2.0 * C->P->Wcc) {
+        t->c.el_hard_fict++;
+        return;
+    }
+    const double eps = sample_moller_eps(&p->rng, T, C->P->Wcc);
+    const double W = eps * T;
+    const double Tp = T - W;
+    const double cp = sqrt(Tp * (T + 2.0 * MC2) / (T * (Tp + 2.0 * MC2)));
+    const double cd = sqrt(W * (T + 2.0 * MC2) / (T * (W + 2.0 * MC2)));
+    const double sp = sqrt(1.0 - cp * cp > 0.0 ? 1.0 - cp * cp : 0.0);
+    const double sd = sqrt(1.0 - cd * cd > 0.0 ? 1.0 - cd * cd : 0.0);
+    const double phi = 2.0 * PI * rng_u(&p->rng);
+    const double cf = cos(phi), sf = sin(phi);
+    double dd[3] = {p->d[0], p->d[1], p->d[2]};
+    orc_rotate(dd, cd, sd, -cf, -sf); /* azimuth phi + pi */
+    orc_rotate(p->d, cp, sp, cf, sf);
+    t->c.el_moller++;
+    p->E = Tp;
+    emit_electron(C, st, t, &p->rng, PT_ELECTRON, W, p->x, p->iv, dd);
+}
+
+static void brems(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
+{
+    const double T = p->E;
+    if (T <= C->P->kc) {
+        t->c.el_hard_fict++;
+        return;
+    }
+    const double k = sample_brems_k(&p->rng, T, C->P->kc);
+    const double th = MC2 / (T + MC2); /* angle of the maximum of the photon DCS */
+    const double phi = 2.0 * PI * rng_u(&p->rng);
+    double dg[3] = {p->d[0], p->d[1], p->d[2]};
+    orc_rotate(dg, cos(th), sin(th), cos(phi), sin(phi));
+    t->c.el_brems++;
+    p->E = T - k;
+    emit_photon(C, st, t, &p->rng, k, p->x, p->iv, dg);
+}
+
+/* Candidate hard event at the end of an event-limited step: accepted with the
+ * Woodcock ratio sigma(T_end)/sigma_hat(T_start) in mass units. */
+static void hard_event(const ctx_t* C, part_t* p, const orc_mat_tables* T, double shm,
+                       stack_t* st, tally_t* t)
+{
+    t->c.el_hard_cand++;
+    int i;
+    double f;
+    orc__grid_pos(p->E, &i, &f);
+    const double sM = lerp(T->sigM, i, f);
+    const double sB = lerp(T->sigB, i, f);
+    const double sH = sM + sB;
+    if (rng_u(&p->rng) * shm < sH) {
+        if (rng_u(&p->rng) * sH < sM) moller(C, p, st, t);
+        else brems(C, p, st, t);
+    } else {
+        t->c.el_hard_fict++;
+    }
+    p->nmfp = -log(rng_u(&p->rng));
+}
+
+static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
+{
+    const orc_problem* P = C->P;
+    for (;;) {
+        const size_t v = lin(C, p->iv);
+        if (p->E <= P->Eabs_e) {
+            deposit(t, v, p->E);
+            t->c.el_absorbed++;
+            if (p->type == PT_POSITRON) annihilate(C, st, t, &p->rng, p->x, p->iv);
+            return;
+        }
+        const orc_mat_tables* T = &C->tab[P->mat[v]];
+        const double rho = C->rho[v];
+        if (!P->csda_mode && p->nmfp < 0.0) p->nmfp = -log(rng_u(&p->rng));
+        const double T0 = p->E;
+        int i;
+        double f;
+        orc__grid_pos(T0, &i, &f);
+        const double RT = lerp(T->R, i, f);
+        const double shm = lerp(T->sigHat, i, f);
+        const double sig_hat = rho * shm;
+        double d_event = INFINITY;
+        if (!P->csda_mode && sig_hat > 0.0) d_event = p->nmfp / sig_hat;
+        int ax;
+        const double d_vox = dist_to_face(C, p->iv, p->x, p->d, &ax);
+        const double d_maxs = P->dmax_s;
+        const double d_maxe = (RT - orc_table_lookup(T->R, (1.0 - P->f_E) * T0)) / rho;
+        const double d_abs = (RT - C->Rabs[P->mat[v]]) / rho;
+        double d = d_vox;
+        int lim = LIM_VOX;
+        if (d_maxs < d) { d = d_maxs; lim = LIM_MAXS; }
+        if (d_maxe < d) { d = d_maxe; lim = LIM_MAXE; }
+        if (d_abs < d) { d = d_abs; lim = LIM_ABS; }
+        if (d_event < d) { d = d_event; lim = LIM_EVENT; }
+
+        int crossed = 0, cax = ax;
+        if (d > 0.0) {
+            double s;
+            if (P->csda_mode) {
+                for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + d * p->d[a];
+                s = d;
+                if (lim == LIM_VOX) crossed = 1;
+            } else {
+                /* random hinge: straight to xi*d, deflect, then the rest */
+                const double xi = rng_u(&p->rng);
+                const double s1 = xi * d;
+                for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + s1 * p->d[a];
+                const double Tplan = orc_range_inverse(T->R, RT - rho * d);
+                const double Tmid = 0.5 * (T0 + Tplan);
+                const double xs = d * rho * orc_table_lookup(T->K1, Tmid);
+                const double A = orc_ms_screening(C->log2A, xs);
+                const double omc = sample_ms(&p->rng, A);
+                const double phi = 2.0 * PI * rng_u(&p->rng);
+                orc_rotate(p->d, 1.0 - omc, sqrt(omc * (2.0 - omc)), cos(phi), sin(phi));
+                const double rem = (1.0 - xi) * d;
+                int ax2;
+                const double dv2 = dist_to_face(C, p->iv, p->x, p->d, &ax2);
+                double s2 = rem;
+                if (dv2 < rem) {
+                    s2 = dv2;
+                    crossed = 1;
+                    cax = ax2;
+                    t->c.el_hinge_trunc++;
+                }
+                for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + s2 * p->d[a];
+                s = s1 + s2;
+            }
+            double Tend;
+            if (lim == LIM_ABS && !crossed) Tend = P->Eabs_e;
+            else Tend = orc_range_inverse(T->R, RT - rho * s);
+            deposit(t, v, T0 - Tend);
+            if (!P->csda_mode) {
+                p->nmfp = p->nmfp - sig_hat * s;
+                if (p->nmfp < 0.0) p->nmfp = 0.0;
+            }
+            t->c.el_steps++;
+            p->E = Tend;
+        } else if (lim == LIM_VOX) {
+            crossed = 1; /* zero-length step on a face: only the index moves */
+        }
+
+        if (crossed) {
+            const int a = cax;
+            const int up = p->d[a] > 0.0;
+            p->x[a] = up ? (double)(p->iv[a] + 1) * C->h[a] : (double)p->iv[a] * C->h[a];
+            p->iv[a] += up ? 1 : -1;
+            t->c.el_boundary++;
+            if (p->iv[a] < 0 || p->iv[a] >= C->n[a]) {
+                t->c.E_escaped += p->E;
+                t->c.el_escaped++;
+                return;
+            }
+            continue;
+        }
+        if (lim == LIM_EVENT) hard_event(C, p, T, shm, st, t);
+    }
+}
+
+/* --- source (Sec. 2.2 "Materials": point source, SSD, field at the surface) --------- */
+
+/* Draws block 0 of stream (seed, h, 0): u1,u2 energy, u3,u4 position.
+ * Returns 0 when the ray misses the phantom. */
+static int source_particle(const ctx_t* C, uint32_t h, part_t* p)
+{
+    const orc_problem* P = C->P;
+    rng_t r;
+    rng_init(&r, C->seed, h, 0u, 0u);
+    const double u1 = rng_u(&r), u2 = rng_u(&r), u3 = rng_u(&r), u4 = rng_u(&r);
+    double E = P->mono_E;
+    if (P->n_bins > 0) {
+        int b = 0;
+        while (b < P->n_bins - 1 && !(C->cdf[b] > u1)) ++b;
+        E = P->edges[b] + u2 * (P->edges[b + 1] - P->edges[b]);
+    }
+    double X[3] = {P->cx + (u3 - 0.5) * P->fx, P->cy + (u4 - 0.5) * P->fy, P->z_field};
+    double d[3] = {0.0, 0.0, 1.0};
+    double tS = -INFINITY; /* ray parameter of the source: parallel beams come from afar */
+    if (P->geometry == 1) {
+        const double a = X[0] - P->sx, b = X[1] - P->sy, c = X[2] - (P->z_field - P->ssd);
+        const double nrm = sqrt(a * a + b * b + c * c);
+        d[0] = a / nrm;
+        d[1] = b / nrm;
+        d[2] = c / nrm;
+        tS = -nrm;
+    }
+    if (P->gantry_deg != 0.0) {
+        /* rotation about the y axis through (iso_x, ., iso_z) */
+        const double g = P->gantry_deg * PI / 180.0;
+        const double cg = cos(g), sg = sin(g);
+        const double px = X[0] - P->iso_x, pz = X[2] - P->iso_z;
+        X[0] = P->iso_x + cg * px + sg * pz;
+        X[2] = P->iso_z - sg * px + cg * pz;
+        const double dx = d[0], dz = d[2];
+        d[0] = cg * dx + sg * dz;
+        d[2] = -sg * dx + cg * dz;
+    }
+    /* the particle enters where the ray from the source first meets the box
+     * (slab method); the field point itself may lie inside the phantom */
+    double t0 = -INFINITY, t1 = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        const double L = (double)C->n[a] * C->h[a];
+        if (d[a] != 0.0) {
+            double ta = (0.0 - X[a]) / d[a], tb = (L - X[a]) / d[a];
+            if (ta > tb) {
+                const double s = ta;
+                ta = tb;
+                tb = s;
+            }
+            if (ta > t0) t0 = ta;
+            if (tb < t1) t1 = tb;
+        } else if (X[a] < 0.0 || X[a] >= L) {
+            t0 = INFINITY;
+        }
+    }
+    p->E = E;
+    if (!(t0 < t1) || t1 <= tS) return 0;
+    const double tt = t0 > tS ? t0 : tS;
+    for (int a = 0; a < 3; ++a) {
+        p->x[a] = X[a] + tt * d[a];
+        p->d[a] = d[a];
+        double fl = floor(p->x[a] / C->h[a]);
+        if (fl < 0.0) fl = 0.0;
+        if (fl > (double)(C->n[a] - 1)) fl = (double)(C->n[a] - 1);
+        p->iv[a] = (int)fl;
+    }
+    p->type = P->particle == 0 ? PT_PHOTON : PT_ELECTRON;
+    p->nmfp = -1.0;
+    rng_init(&p->rng, C->seed, h, 0u, 1u); /* transport continues at block 1 */
+    return 1;
+}
+
+static void run_history(const ctx_t* C, uint32_t h, stack_t* st, tally_t* t)
+{
+    part_t p;
+    const int hit = source_particle(C, h, &p);
+    t->c.E_incident += p.E;
+    if (!hit) {
+        t->c.E_escaped += p.E;
+        t->c.src_miss++;
+        return;
+    }
+    if (p.type != PT_PHOTON && C->P->kerma_mode) {
+        deposit(t, lin(C, p.iv), p.E);
+        return;
+    }
+    st->n = 0;
+    stack_push(st, &p);
+    while (st->n > 0) {
+        part_t q = st->a[--st->n];
+        if (q.type == PT_PHOTON) transport_photon(C, &q, st, t);
+        else transport_electron(C, &q, st, t);
+    }
+}
+
+/* --- context -------------------------------------------------------------------- */
+static int ctx_init(ctx_t* C, const orc_problem* P, uint32_t seed)
+{
+    memset(C, 0, sizeof *C);
+    if (!P || P->nx <= 0 || P->ny <= 0 || P->nz <= 0 || P->n_mats <= 0 || !P->density || !P->mat)
+        return -1;
+    C->P = P;
+    C->seed = seed;
+    C->n[0] = P->nx;
+    C->n[1] = P->ny;
+    C->n[2] = P->nz;
+    C->h[0] = P->dx;
+    C->h[1] = P->dy;
+    C->h[2] = P->dz;
+    C->nvox = (size_t)P->nx * (size_t)P->ny * (size_t)P->nz;
+    C->rho = (double*)malloc(C->nvox * sizeof(double));
+    C->tab = (orc_mat_tables*)calloc((size_t)P->n_mats, sizeof(orc_mat_tables));
+    C->Rabs = (double*)calloc((size_t)P->n_mats, sizeof(double));
+    double* rmax = (double*)calloc((size_t)P->n_mats, sizeof(double));
+    for (size_t v = 0; v < C->nvox; ++v) {
+        if (P->mat[v] >= P->n_mats || !(P->density[v] > 0.0f)) {
+            free(rmax);
+            return -1;
+        }
+        C->rho[v] = (double)P->density[v];
+        if (C->rho[v] > rmax[P->mat[v]]) rmax[P->mat[v]] = C->rho[v];
+    }
+    for (int m = 0; m < P->n_mats; ++m) {
+        orc_build_material(&P->mats[m], P->Wcc, P->kc, &C->tab[m]);
+        C->Rabs[m] = orc_table_lookup(C->tab[m].R, P->Eabs_e);
+    }
+    /* photon majorant: node-wise maximum of rho_max(m) * mu_tot(m) over the
+     * materials present; its interpolant bounds every material's */
+    for (int i = 0; i < ORC_NE; ++i) {
+        double mx = 0.0;
+        for (int m = 0; m < P->n_mats; ++m) {
+            const double val = rmax[m] * C->tab[m].muTot[i];
+            if (val > mx) mx = val;
+        }
+        C->muhat[i] = mx;
+    }
+    free(rmax);
+    orc_build_ms_table(C->log2A);
+    if (P->n_bins > 0) {
+        C->cdf = (double*)malloc((size_t)P->n_bins * sizeof(double));
+        double s = 0.0;
+        for (int b = 0; b < P->n_bins; ++b) {
+            s += P->weights[b];
+            C->cdf[b] = s;
+        }
+        for (int b = 0; b < P->n_bins; ++b) C->cdf[b] = C->cdf[b] / s;
+    }
+    return 0;
+}
+
+static void ctx_free(ctx_t* C)
+{
+    free(C->rho);
+    free(C->tab);
+    free(C->Rabs);
+    free(C->cdf);
+}
+
+static void counters_add(orc_counters* a, const orc_counters* b)
+{
+    a->ph_flights += b->ph_flights;
+    a->ph_fictitious += b->ph_fictitious;
+    a->ph_compton += b->ph_compton;
+    a->ph_photo += b->ph_photo;
+    a->ph_pair += b->ph_pair;
+    a->ph_cutoff += b->ph_cutoff;
+    a->ph_escaped += b->ph_escaped;
+    a->el_steps += b->el_steps;
+    a->el_hard_cand += b->el_hard_cand;
+    a->el_hard_fict += b->el_hard_fict;
+    a->el_moller += b->el_moller;
+    a->el_brems += b->el_brems;
+    a->el_absorbed += b->el_absorbed;
+    a->el_escaped += b->el_escaped;
+    a->el_boundary += b->el_boundary;
+    a->el_hinge_trunc += b->el_hinge_trunc;
+    a->pos_annihil += b->pos_annihil;
+    a->push_ph += b->push_ph;
+    a->push_el += b->push_el;
+    a->src_miss += b->src_miss;
+    a->E_incident += b->E_incident;
+    a->E_deposited += b->E_deposited;
+    a->E_escaped += b->E_escaped;
+    a->E_pair_rest += b->E_pair_rest;
+    a->E_annih_rest += b->E_annih_rest;
+}
+
+int orc_run(const orc_problem* P, uint64_t N, uint32_t seed, uint32_t h0, int nthreads,
+            double* dose, double* dose2, orc_counters* out)
+{
+    if (N == 0 || P->n_batches <= 0 || !dose || !dose2 || !out) return -1;
+    if ((uint64_t)h0 + N > 4294967296ull) return -1;
+    ctx_t C;
+    if (ctx_init(&C, P, seed) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    const int B = P->n_batches;
+    const int nt = nthreads > 0 ? nthreads : 1;
+    const double V = P->dx * P->dy * P->dz;
+    double** grids = (double**)calloc((size_t)nt, sizeof(double*));
+    orc_counters* tc = (orc_counters*)calloc((size_t)nt, sizeof(orc_counters));
+    double* Eb = (double*)malloc(C.nvox * sizeof(double));
+    for (int k = 0; k < nt; ++k) grids[k] = (double*)malloc(C.nvox * sizeof(double));
+    memset(dose, 0, C.nvox * sizeof(double));
+    memset(dose2, 0, C.nvox * sizeof(double));
+    memset(out, 0, sizeof *out);
+
+    for (int b = 0; b < B; ++b) {
+        /* batch b holds the relative indices i with floor(i*B/N) == b */
+        const uint64_t i0 = ((uint64_t)b * N + (uint64_t)B - 1) / (uint64_t)B;
+        const uint64_t i1 = ((uint64_t)(b + 1) * N + (uint64_t)B - 1) / (uint64_t)B;
+        const uint64_t Nb = i1 - i0;
+        if (Nb == 0) continue;
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+        for (int k = 0; k < nt; ++k) {
+            tally_t t;
+            t.grid = grids[k];
+            memset(t.grid, 0, C.nvox * sizeof(double));
+            memset(&t.c, 0, sizeof t.c);
+            stack_t st = {NULL, 0, 0};
+            const uint64_t a0 = i0 + (uint64_t)k * Nb / (uint64_t)nt;
+            const uint64_t a1 = i0 + (uint64_t)(k + 1) * Nb / (uint64_t)nt;
+            for (uint64_t i = a0; i < a1; ++i) run_history(&C, (uint32_t)(h0 + i), &st, &t);
+            free(st.a);
+            tc[k] = t.c;
+        }
+        /* fixed-order reduction over tasks */
+        memcpy(Eb, grids[0], C.nvox * sizeof(double));
+        for (int k = 1; k < nt; ++k)
+            for (size_t v = 0; v < C.nvox; ++v) Eb[v] += grids[k][v];
+        for (int k = 0; k < nt; ++k) counters_add(out, &tc[k]);
+        for (size_t v = 0; v < C.nvox; ++v) {
+            dose[v] += Eb[v] / (C.rho[v] * V * (double)N);
+            const double db = Eb[v] / (C.rho[v] * V * (double)Nb);
+            dose2[v] += db * db;
+        }
+    }
+    for (int k = 0; k < nt; ++k) free(grids[k]);
+    free(grids);
+    free(tc);
+    free(Eb);
+    ctx_free(&C);
+    return 0;
+}
+
+/* --- test entry points ------------------------------------------------------------ */
+
+int orc_first_interaction(const orc_problem* P, uint32_t seed, uint32_t h0, uint32_t n,
+                          double* pos, int* type, uint64_t* n_fict)
+{
+    ctx_t C;
+    if (ctx_init(&C, P, seed) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    tally_t t;
+    t.grid = (double*)calloc(C.nvox, sizeof(double));
+    memset(&t.c, 0, sizeof t.c);
+    for (uint32_t k = 0; k < n; ++k) {
+        part_t p;
+        type[k] = 0;
+        pos[3 * k] = pos[3 * k + 1] = pos[3 * k + 2] = NAN;
+        if (!source_particle(&C, h0 + k, &p)) continue;
+        size_t v;
+        int i;
+        double f;
+        if (woodcock(&C, &p, &t, &v, &i, &f)) type[k] = select_type(&C, &p, v, i, f);
+        for (int a = 0; a < 3; ++a) pos[3 * k + a] = p.x[a];
+    }
+    *n_fict = t.c.ph_fictitious;
+    free(t.grid);
+    ctx_free(&C);
+    return 0;
+}
+
+void orc_sample_source(const orc_problem* P, uint32_t seed, uint32_t h0, uint32_t n, double* E,
+                       double* x, double* d)
+{
+    ctx_t C;
+    if (ctx_init(&C, P, seed) != 0) {
+        ctx_free(&C);
+        return;
+    }
+    for (uint32_t k = 0; k < n; ++k) {
+        part_t p;
+        const int hit = source_particle(&C, h0 + k, &p);
+        E[k] = hit ? p.E : 0.0;
+        for (int a = 0; a < 3; ++a) {
+            x[3 * k + a] = hit ? p.x[a] : NAN;
+            d[3 * k + a] = hit ? p.d[a] : NAN;
+        }
+    }
+    ctx_free(&C);
+}
+
+void orc_sample_compton(double E, uint32_t seed, uint32_t n, double* eps, double* cost,
+                        uint32_t* words)
+{
+    for (uint32_t k = 0; k < n; ++k) {
+        rng_t r;
+        rng_init(&r, seed, k, 0u, 0u);
+        double t;
+        eps[k] = sample_compton_eps(&r, E / MC2, &t);
+        cost[k] = 1.0 - t;
+        words[k] = 4u * (r.n - 1u) + (uint32_t)r.nw;
+    }
+}
+
+void orc_sample_moller(double T, double Wcc, uint32_t seed, uint32_t n, double* eps)
+{
+    for (uint32_t k = 0; k < n; ++k) {
+        rng_t r;
+        rng_init(&r, seed, k, 0u, 0u);
+        eps[k] = sample_moller_eps(&r, T, Wcc);
+    }
+}
+
+void orc_sample_brems(double T, double kc, uint32_t seed, uint32_t n, double* k)
+{
+    for (uint32_t j = 0; j < n; ++j) {
+        rng_t r;
+        rng_init(&r, seed, j, 0u, 0u);
+        k[j] = sample_brems_k(&r, T, kc);
+    }
+}
+
+void orc_sample_ms(const double* log2A, double x, uint32_t seed, uint32_t n, double* omc)
+{
+    const double A = orc_ms_screening(log2A, x);
+    for (uint32_t k = 0; k < n; ++k) {
+        rng_t r;
+        rng_init(&r, seed, k, 0u, 0u);
+        omc[k] = sample_ms(&r, A);
+    }
+}

@@ -1,0 +1,212 @@
+"""Seeded synthetic inputs: phantoms, material compositions, beam spectra and
+sources for the paper's workloads.
+
+This module holds input data and generators only, none of the transport
+arithmetic. Both the GPU path and the CPU oracle receive what it builds.
+
+Workloads (the paper, Sec. 2.2 "Materials": 32 cm cubes of 0.25 cm voxels; a
+homogeneous water phantom, a water/bone/lung/water slab and a half slab; point
+source at SSD 100 cm; 6 MV spectrum or 15 MeV electrons):
+
+* ``water_e15``: 15 MeV electrons, 1x1 cm^2 parallel beam along +z,
+  water 32^3 voxels of 0.5 cm.
+* ``slab_6mv``: 6 MV photons, 10x10 cm^2 field at SSD 100, 128^3 voxels of
+  0.25 cm, water [0,2) / bone 1.85 [2,4) / lung 0.26 [4,10) / water [10,32) cm.
+* ``halfslab_e15``: 15 MeV electrons, 10x10 cm^2 at SSD 100, 256^3 voxels of
+  0.2 cm of water with a bone (1.85) block where x < 25.6 cm and 2 <= z < 5 cm.
+* ``ct_beamlets``: 256x256x160 voxels of 0.2 cm, 12 seeded ellipsoids with
+  densities 0.2-1.9 g/cm^3, 512 beamlets of 0.5x0.5 cm^2 from 8 gantry angles.
+
+Arrays are indexed (z, y, x): x is the fastest axis in memory.
+"""
+import numpy as np
+
+# Element data: (Z, atomic weight g/mol).
+_ELEM = {"H": (1, 1.008), "C": (6, 12.011), "N": (7, 14.007), "O": (8, 15.999),
+         "Na": (11, 22.990), "Mg": (12, 24.305), "P": (15, 30.974), "S": (16, 32.06),
+         "Cl": (17, 35.45), "K": (19, 39.098), "Ca": (20, 40.078)}
+
+
+def _material(name, comp, I_eV, rho_nom):
+    Z = [_ELEM[e][0] for e, _ in comp]
+    A = [_ELEM[e][1] for e, _ in comp]
+    w = np.array([f for _, f in comp], dtype=np.float64)
+    w = w / w.sum()
+    return {"name": name, "Z": Z, "A": A, "w": list(w), "I_eV": float(I_eV),
+            "rho_nom": float(rho_nom)}
+
+
+# Compositions by mass fraction (ICRU-44-like values) and mean excitation energies.
+WATER = _material("water", [("H", 0.111894), ("O", 0.888106)], 75.0, 1.0)
+LUNG = _material("lung", [("H", 0.103), ("C", 0.105), ("N", 0.031), ("O", 0.749),
+                          ("Na", 0.002), ("P", 0.002), ("S", 0.003), ("Cl", 0.003),
+                          ("K", 0.002)], 75.3, 0.26)
+BONE = _material("bone", [("H", 0.034), ("C", 0.155), ("N", 0.042), ("O", 0.435),
+                          ("Na", 0.001), ("Mg", 0.002), ("P", 0.103), ("S", 0.003),
+                          ("Ca", 0.225)], 110.0, 1.85)
+MATERIALS = [WATER, LUNG, BONE]   # material ids 0, 1, 2
+MAT_WATER, MAT_LUNG, MAT_BONE = 0, 1, 2
+
+
+def material_from_density(rho):
+    """CT-like assignment: rho < 0.5 lung, 0.5 <= rho < 1.2 water, >= 1.2 bone."""
+    m = np.full(rho.shape, MAT_WATER, dtype=np.uint8)
+    m[rho < 0.5] = MAT_LUNG
+    m[rho >= 1.2] = MAT_BONE
+    return m
+
+
+def _phantom(density, material, voxel):
+    return {"density": np.ascontiguousarray(density, dtype=np.float32),
+            "material": np.ascontiguousarray(material, dtype=np.uint8),
+            "shape": tuple(int(s) for s in density.shape),
+            "voxel": tuple(float(v) for v in voxel),
+            "materials": MATERIALS}
+
+
+def water_phantom(n=(32, 32, 32), h=0.5, rho=1.0):
+    nz, ny, nx = n
+    d = np.full((nz, ny, nx), rho, dtype=np.float32)
+    return _phantom(d, np.full(d.shape, MAT_WATER, np.uint8), (h, h, h))
+
+
+def layered_phantom(n, h, layers):
+    """layers: list of (z_start_cm, z_end_cm, material_id, density)."""
+    nz, ny, nx = n
+    d = np.empty((nz, ny, nx), dtype=np.float32)
+    m = np.empty((nz, ny, nx), dtype=np.uint8)
+    zc = (np.arange(nz) + 0.5) * h
+    for z0, z1, mid, rho in layers:
+        sel = (zc >= z0) & (zc < z1)
+        d[sel] = rho
+        m[sel] = mid
+    return _phantom(d, m, (h, h, h))
+
+
+def slab_phantom(n=128, h=0.25):
+    """Water [0,2) / bone 1.85 [2,4) / lung 0.26 [4,10) / water [10, end) cm."""
+    end = n * h + 1.0
+    return layered_phantom((n, n, n), h, [(0.0, 2.0, MAT_WATER, 1.0), (2.0, 4.0, MAT_BONE, 1.85),
+                                          (4.0, 10.0, MAT_LUNG, 0.26),
+                                          (10.0, end, MAT_WATER, 1.0)])
+
+
+def halfslab_phantom(n=256, h=0.2, x_split=None):
+    """Water with a bone (1.85) block filling x < x_split for depths 2 <= z < 5 cm."""
+    x_split = n * h / 2.0 if x_split is None else x_split
+    d = np.ones((n, n, n), dtype=np.float32)
+    m = np.zeros((n, n, n), dtype=np.uint8)
+    zc = (np.arange(n) + 0.5) * h
+    xc = (np.arange(n) + 0.5) * h
+    zs = (zc >= 2.0) & (zc < 5.0)
+    xs = xc < x_split
+    sel = zs[:, None, None] & xs[None, None, :]
+    sel = np.broadcast_to(sel, d.shape)
+    d[sel] = 1.85
+    m[sel] = MAT_BONE
+    return _phantom(d, m, (h, h, h))
+
+
+def ellipsoid_phantom(shape=(160, 256, 256), h=0.2, n_ell=12, seed=1):
+    """CT-like phantom: water background and n_ell seeded ellipsoids (centres in
+    the inner 80 %, semi-axes U[1,6] cm, random rotation, density U[0.2,1.9]),
+    painted in order; material by density thresholds."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    L = np.array([nx * h, ny * h, nz * h])
+    d = np.ones(shape, dtype=np.float32)
+    zc = (np.arange(nz) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    xc = (np.arange(nx) + 0.5) * h
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    for _ in range(n_ell):
+        c = L * (0.1 + 0.8 * rng.random(3))
+        ax = rng.uniform(1.0, 6.0, 3)
+        q, _r = np.linalg.qr(rng.normal(size=(3, 3)))
+        rho = rng.uniform(0.2, 1.9)
+        P = np.stack([X - c[0], Y - c[1], Z - c[2]], axis=-1) @ q
+        inside = ((P / ax) ** 2).sum(-1) <= 1.0
+        d[inside] = rho
+    return _phantom(d, material_from_density(d), (h, h, h))
+
+
+def spectrum_6mv(n_bins=64, e_lo=0.2, e_hi=6.0, seed=1):
+    """Bremsstrahlung-shaped 6 MV spectrum: equal bins on [e_lo, e_hi], weight
+    w_i ~ ((6 - E_i)/E_i)(1 - exp(-(E_i/0.5)^2))(1 + 0.05(2 r_i - 1)) at bin
+    centres E_i, r_i from default_rng(seed)."""
+    edges = np.linspace(e_lo, e_hi, n_bins + 1)
+    Ec = 0.5 * (edges[:-1] + edges[1:])
+    r = np.random.default_rng(seed).random(n_bins)
+    w = ((e_hi - Ec) / Ec) * (1.0 - np.exp(-(Ec / 0.5) ** 2)) * (1.0 + 0.05 * (2 * r - 1))
+    w = np.maximum(w, 0.0)
+    return edges, w / w.sum()
+
+
+def electron_beam(E, field, centre, parallel=True, ssd=100.0):
+    fx, fy = field
+    cx, cy = centre
+    return {"particle": 1, "n_bins": 0, "mono_E": float(E), "geometry": 0 if parallel else 1,
+            "ssd": ssd, "z_field": 0.0, "fx": fx, "fy": fy, "cx": cx, "cy": cy,
+            "sx": cx, "sy": cy, "gantry_deg": 0.0, "iso_x": cx, "iso_z": 0.0}
+
+
+def photon_beam(field, centre, spectrum=None, mono_E=None, parallel=False, ssd=100.0):
+    fx, fy = field
+    cx, cy = centre
+    src = {"particle": 0, "geometry": 0 if parallel else 1, "ssd": ssd, "z_field": 0.0,
+           "fx": fx, "fy": fy, "cx": cx, "cy": cy, "sx": cx, "sy": cy, "gantry_deg": 0.0,
+           "iso_x": cx, "iso_z": 0.0}
+    if spectrum is not None:
+        edges, w = spectrum
+        src.update(n_bins=len(w), edges=np.asarray(edges, np.float64),
+                   weights=np.asarray(w, np.float64), mono_E=0.0)
+    else:
+        src.update(n_bins=0, mono_E=float(mono_E))
+    return src
+
+
+def config(name, scale=1.0):
+    """The named workload as (phantom, source, n_histories). ``scale`` shrinks the
+    history count (for tests) without touching geometry."""
+    if name == "water_e15":
+        ph = water_phantom((32, 32, 32), 0.5)
+        src = electron_beam(15.0, (1.0, 1.0), (8.0, 8.0), parallel=True)
+        n = 10_000
+    elif name == "slab_6mv":
+        ph = slab_phantom(128, 0.25)
+        src = photon_beam((10.0, 10.0), (16.0, 16.0), spectrum=spectrum_6mv())
+        n = 10_000_000
+    elif name == "halfslab_e15":
+        ph = halfslab_phantom(256, 0.2)
+        src = electron_beam(15.0, (10.0, 10.0), (25.6, 25.6), parallel=False)
+        n = 100_000_000
+    else:
+        raise KeyError(name)
+    return ph, src, max(1, int(round(n * scale)))
+
+
+def beamlets(phantom, n_angles=8, grid=8, size=0.5, sad=100.0, count_range=(100_000, 1_000_000),
+             seed=2):
+    """Beamlet list for the batched workload: n_angles gantry angles about y
+    through the phantom centre, a grid x grid array of size x size cm^2
+    beamlets on the isocentre plane, 6 MV spectrum, seeded history counts."""
+    nz, ny, nx = phantom["shape"]
+    hz, hy, hx = phantom["voxel"]
+    iso = np.array([nx * hx / 2.0, ny * hy / 2.0, nz * hz / 2.0])
+    counts = np.random.default_rng(seed).integers(count_range[0], count_range[1] + 1,
+                                                  n_angles * grid * grid)
+    spec = spectrum_6mv()
+    out = []
+    k = 0
+    for a in range(n_angles):
+        g = 360.0 * a / n_angles
+        for j in range(grid):
+            for i in range(grid):
+                cx = iso[0] + (i - (grid - 1) / 2.0) * size
+                cy = iso[1] + (j - (grid - 1) / 2.0) * size
+                src = photon_beam((size, size), (cx, cy), spectrum=spec, ssd=sad)
+                src.update(z_field=float(iso[2]), sx=float(iso[0]), sy=float(iso[1]),
+                           gantry_deg=g, iso_x=float(iso[0]), iso_z=float(iso[2]))
+                out.append((src, int(counts[k])))
+                k += 1
+    return out
