@@ -1,0 +1,177 @@
+/*
+ * omc.h -- C ABI of the MI355X (gfx950) coupled photon-electron Monte Carlo dose
+ * engine. The method is that of Tian et al., "An OpenCL-based Monte Carlo dose
+ * calculation engine (oclMC) for coupled photon-electron transport"
+ * (arXiv 1503.01722).
+ *
+ * Conventions for every entry point:
+ *  - The return value is a status: OMC_OK (0) or a negative OMC_E* code. Nothing
+ *    aborts or throws across this boundary. On error the context is unchanged
+ *    (except for its last-error string) unless stated otherwise.
+ *  - Host arrays passed in are copied during the call; the caller keeps
+ *    ownership and may free them afterwards.
+ *  - Host output arrays are allocated by the caller. Device output pointers are
+ *    caller-owned device memory (for example a torch tensor's data_ptr()) valid
+ *    on the stream given to the call.
+ *  - A context is bound to the device current at omc_create and is not
+ *    thread-safe: one thread at a time per context.
+ *  - Units: MeV, cm, g/cm^3. Dose is MeV/g per source history (Sec. 2.2
+ *    "Materials" of the paper reports dose in MeV/g per source particle).
+ *  - Phantom arrays are nx*ny*nz values with x fastest, then y, then z.
+ */
+#ifndef OMC_H
+#define OMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    OMC_OK = 0,
+    OMC_EINVAL = -1,   /* invalid argument (sizes, NaN or non-positive density, ...) */
+    OMC_ENOMEM = -2,   /* device or host allocation failed */
+    OMC_EDEVICE = -3,  /* HIP runtime error or no device */
+    OMC_ESTATE = -4,   /* call out of order (e.g. omc_run before omc_set_source) */
+    OMC_EQUEUE = -5,   /* a secondary-particle queue overflowed; raise queue_factor */
+    OMC_ENUMERIC = -6, /* non-finite result or energy ledger violated */
+    OMC_EUNSUP = -7    /* unsupported configuration (e.g. too many materials) */
+};
+
+#define OMC_MAX_MATERIALS 8
+#define OMC_MAX_DIM 1024
+#define OMC_MAX_BATCHES 64
+#define OMC_NE 512      /* energy nodes, uniform in log2 E over [0.01, 20] MeV */
+#define OMC_NA 512      /* multiple-scattering screening table nodes */
+#define OMC_TABLE_ROWS 11
+
+typedef struct omc_ctx omc_ctx;
+
+/* A material as an element composition (Sec. 2.1: the physics data of each
+ * material are generated from a user-defined composition). */
+typedef struct {
+    int n_elem;
+    const int* Z;            /* atomic numbers, n_elem */
+    const double* A;         /* atomic weights g/mol, n_elem */
+    const double* w_mass;    /* mass fractions, n_elem (normalised by the caller) */
+    double I_eV;             /* mean excitation energy */
+    double rho_nominal;      /* density used for the density-effect correction */
+} omc_material;
+
+/* Source (Sec. 2.2 "Materials": point source, SSD 100 cm, field defined at the
+ * phantom surface, 6 MV spectrum or 15 MeV electrons). A field point is drawn
+ * uniformly on an fx x fy rectangle centred at (cx, cy) in the plane z = z_field
+ * of the gantry-0 frame; a point source sits at (sx, sy, z_field - ssd). The
+ * frame is then rotated by gantry_deg about the y axis through (iso_x, iso_z),
+ * and the particle enters where the ray from the source first meets the box. */
+typedef struct {
+    int particle;            /* 0 photon, 1 electron */
+    int n_bins;              /* spectrum bins; 0 = mono-energetic mono_E */
+    const double* edges;     /* n_bins + 1 bin edges, MeV, increasing */
+    const double* weights;   /* n_bins non-negative weights (need not be normalised) */
+    double mono_E;           /* MeV, used when n_bins == 0 */
+    int geometry;            /* 0 parallel beam along the axis, 1 point source */
+    double ssd;              /* point source to field plane distance, cm */
+    double z_field;          /* field plane z in the gantry-0 frame, cm */
+    double fx, fy;           /* field size on the field plane, cm */
+    double cx, cy;           /* field centre, cm */
+    double sx, sy;           /* focal spot x, y (point source), cm */
+    double gantry_deg;       /* rotation about y; 0 = beam along +z */
+    double iso_x, iso_z;     /* rotation axis position, cm */
+} omc_source;
+
+/* Transport parameters (Sec. 2.1 step limits; Sec. 2.2 "Materials" cut-offs)
+ * and launch shape. Fill with omc_default_params() and override. */
+typedef struct {
+    double Eabs_e;           /* electron/positron absorption energy, MeV (0.2) */
+    double Eabs_g;           /* photon absorption energy, MeV (0.05) */
+    double Wcc;              /* Moller hard-event threshold, MeV (0.05) */
+    double kc;               /* bremsstrahlung hard-event threshold, MeV (0.2) */
+    double dmax_s;           /* maximum electron step, cm (0.5) */
+    double f_E;              /* maximum fractional energy loss per step (0.25) */
+    int n_batches;           /* batches for the uncertainty estimate (10) */
+    int parity_fp64;         /* 1: transport in FP64 (bit-level parity build) */
+    int kerma_mode;          /* 1: e-/e+ deposited where created */
+    int csda_mode;           /* 1: no hinge, no multiple scattering, no hard events */
+    int block_size;          /* work-items per work-group (256); multiple of 64 */
+    int blocks_per_cu;       /* resident work-groups per CU for the transport grid (4) */
+    int chunk_histories;     /* histories per source chunk (0 = automatic) */
+    int queue_factor;        /* secondary queue capacity per source history (8) */
+    int timing;              /* 1: record per-kernel HIP event times */
+} omc_params;
+
+/* Per-run event counters and the energy ledger (all from the last run). */
+typedef struct {
+    uint64_t ph_flights, ph_fictitious, ph_compton, ph_photo, ph_pair, ph_cutoff, ph_escaped;
+    uint64_t el_steps, el_hard_cand, el_hard_fict, el_moller, el_brems, el_absorbed, el_escaped;
+    uint64_t el_boundary, el_hinge_trunc, pos_annihil, push_ph, push_el, src_miss;
+    uint64_t watchdog;   /* particles stopped by the per-particle step bound (2^20) */
+    double E_incident, E_deposited, E_escaped, E_pair_rest, E_annih_rest;
+    uint64_t queue_hwm_ph, queue_hwm_el; /* largest queue occupancy seen */
+    uint32_t iterations;                 /* photon/electron generations launched */
+} omc_counters;
+
+/* Per-kernel timing of the last run (params.timing == 1), HIP events on the
+ * run's stream. */
+typedef struct {
+    uint32_t launches[4];    /* 0 source, 1 photon, 2 electron, 3 fold */
+    double total_ms[4];
+    double run_ms;           /* whole run, first launch to last */
+} omc_timing;
+
+void omc_default_params(omc_params* p);
+
+/* Create a context on the current HIP device. density: g/cm^3, finite and > 0;
+ * material: ids < n_mats; mats: n_mats compositions (1 <= n_mats <= 8). Sizes:
+ * 1 <= nx,ny,nz <= 1024, voxel sizes > 0. Builds the closed-form tables
+ * (Sec. 2.1) and uploads phantom and tables. */
+int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
+               const float* density, const uint8_t* material, const omc_material* mats,
+               int n_mats);
+
+/* Set the source (copied). Spectrum weights must have a positive sum. */
+int omc_set_source(omc_ctx* ctx, const omc_source* src);
+
+/* Set parameters (copied). Rebuilds the electron tables when Wcc or kc change. */
+int omc_set_params(omc_ctx* ctx, const omc_params* p);
+
+/* Transport histories h0 .. h0+n-1 with streams keyed by (seed, h) and write
+ * dose (MeV/g per history) and dose2 = sum over batches of the squared batch
+ * dose, both nx*ny*nz doubles in caller-owned host memory. h0 + n <= 2^32.
+ * Blocks until done. */
+int omc_run(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* dose,
+            double* dose2);
+
+/* As omc_run, with dose and dose2 in caller-owned device memory, launched on
+ * hip_stream (a hipStream_t; NULL = default stream). Returns when the run is
+ * complete on that stream. */
+int omc_run_device(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* d_dose,
+                   double* d_dose2, void* hip_stream);
+
+int omc_get_counters(const omc_ctx* ctx, omc_counters* out);
+int omc_get_timing(const omc_ctx* ctx, omc_timing* out);
+
+/* Words of the Philox4x32-10 stream keyed by (seed, h) for particle id q,
+ * blocks n0 .. n0+nblocks-1, computed on the GPU: out holds 4*nblocks words
+ * (host memory, caller-owned). */
+int omc_debug_philox(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
+                     uint32_t* out);
+
+/* Host-only (no device needed): the engine's own table builder. out receives
+ * OMC_TABLE_ROWS x OMC_NE doubles in the row order muC, muPE, muPair, muTot,
+ * Scol, Srad, R, sigM, sigB, sigHat, K1 (units cm^2/g, MeV cm^2/g, g/cm^2). */
+int omc_host_tables(const omc_material* mat, double Wcc, double kc, double* out);
+/* Host-only: log2 of the screening parameter A at OMC_NA nodes uniform in
+ * log2(s/lambda_1) over [-24, 3]. */
+int omc_host_ms_table(double* out);
+
+/* Last error message of ctx (or of the calling thread when ctx is NULL). */
+const char* omc_last_error(const omc_ctx* ctx);
+
+void omc_destroy(omc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,89 @@
+// kernels_f32.hip -- production transport in FP32 (FP64 tally), plus the
+// precision-independent helper kernels: batch fold, queue reset and the Philox
+// debug kernel.
+#include "kernels_impl.hpp"
+
+namespace omc {
+
+template struct Launch<float>;
+
+// dose_v = sum_b E_vb / (rho_v V N); dose2_v = sum_b (E_vb / (rho_v V N_b))^2,
+// batches in order (Sec. 3.1 reports sigma_D per voxel; batch method).
+struct BatchSizes {
+    double nb[64];
+};
+
+__global__ void __launch_bounds__(256)
+fold_kernel(const double* __restrict__ grid, const float* __restrict__ rho, size_t nvox, int B,
+            BatchSizes nbs, double V, double N, double* __restrict__ dose,
+            double* __restrict__ dose2)
+{
+    const size_t stride = size_t(gridDim.x) * blockDim.x;
+    for (size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nvox; v += stride) {
+        const double mV = double(rho[v]) * V;
+        double d = 0.0, d2 = 0.0;
+        for (int b = 0; b < B; ++b) {
+            if (!(nbs.nb[b] > 0.0)) continue;
+            const double e = grid[size_t(b) * nvox + v];
+            d += e / (mV * N);
+            const double db = e / (mV * nbs.nb[b]);
+            d2 += db * db;
+        }
+        dose[v] = d;
+        dose2[v] = d2;
+    }
+}
+
+int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,
+                double V, double n_total, double* dose, double* dose2, void* stream)
+{
+    if (B < 1 || B > 64) return -1;
+    BatchSizes nbs{};
+    for (int b = 0; b < B; ++b) nbs.nb[b] = nb[b];
+    const int block = 256;
+    size_t blocks = (nvox + block - 1) / block;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fold_kernel, dim3(unsigned(blocks)), dim3(block), 0, (hipStream_t)stream,
+                       grid, rho, nvox, B, nbs, V, n_total, dose, dose2);
+    return detail::launch_status();
+}
+
+// Clear {count, head} of the queues selected by mask (bit q -> queue q).
+__global__ void queue_reset_kernel(uint32_t* ctrl, int mask)
+{
+    const int q = threadIdx.x;
+    if (q < 4 && (mask >> q) & 1) {
+        ctrl[2 * q] = 0u;
+        ctrl[2 * q + 1] = 0u;
+    }
+}
+
+int launch_queue_reset(uint32_t* ctrl, int mask, void* stream)
+{
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, ctrl, mask);
+    return detail::launch_status();
+}
+
+__global__ void philox_debug_kernel(uint32_t seed, uint32_t h, uint32_t qlo, uint32_t qhi,
+                                    uint32_t n0, uint32_t nblocks, uint32_t* out)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    uint32_t o0, o1, o2, o3;
+    Stream::block(n0 + b, qlo, qhi, 0u, seed, h, o0, o1, o2, o3);
+    out[4 * size_t(b) + 0] = o0;
+    out[4 * size_t(b) + 1] = o1;
+    out[4 * size_t(b) + 2] = o2;
+    out[4 * size_t(b) + 3] = o3;
+}
+
+int launch_philox_debug(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
+                        uint32_t* out, void* stream)
+{
+    const unsigned grid = (nblocks + 255) / 256;
+    hipLaunchKernelGGL(philox_debug_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, seed,
+                       h, uint32_t(q), uint32_t(q >> 32), n0, nblocks, out);
+    return detail::launch_status();
+}
+
+}  // namespace omc

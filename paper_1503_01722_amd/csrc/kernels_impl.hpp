@@ -1,0 +1,45 @@
+// kernels_impl.hpp -- host launchers for one transport precision R. Included by
+// one translation unit per precision (FP32 production, FP64 parity).
+#pragma once
+
+#include "device.hpp"
+
+namespace omc {
+
+namespace detail {
+inline int launch_status()
+{
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+}  // namespace detail
+
+template <typename R>
+int Launch<R>::source(const KernelArgs<R>& a, int grid, int block, void* stream)
+{
+    hipLaunchKernelGGL(source_kernel<R>, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+    return detail::launch_status();
+}
+
+template <typename R>
+int Launch<R>::photon(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream)
+{
+    if (lds > 65536 &&
+        hipFuncSetAttribute((const void*)photon_kernel<R>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return -1;
+    hipLaunchKernelGGL(photon_kernel<R>, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
+    return detail::launch_status();
+}
+
+template <typename R>
+int Launch<R>::electron(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream)
+{
+    if (lds > 65536 &&
+        hipFuncSetAttribute((const void*)electron_kernel<R>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return -1;
+    hipLaunchKernelGGL(electron_kernel<R>, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
+    return detail::launch_status();
+}
+
+}  // namespace omc

@@ -1,0 +1,249 @@
+"""Python binding of the C ABI in include/omc.h (argument marshalling only).
+
+Every step of the transport runs in the HIP library ``_lib/libomc.so``; this
+module only converts numpy arrays, dictionaries and torch device buffers into
+the plain pointers and structs the C functions take. If the library is not
+built, loading fails with an error: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libomc.so")
+
+OMC_OK, OMC_EINVAL, OMC_ENOMEM, OMC_EDEVICE, OMC_ESTATE, OMC_EQUEUE, OMC_ENUMERIC, OMC_EUNSUP = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+NE = 512
+NA = 512
+TABLE_ROWS = ["muC", "muPE", "muPair", "muTot", "Scol", "Srad", "R", "sigM", "sigB", "sigHat",
+              "K1"]
+EXPORTS = ["omc_default_params", "omc_create", "omc_set_source", "omc_set_params", "omc_run",
+           "omc_run_device", "omc_get_counters", "omc_get_timing", "omc_debug_philox",
+           "omc_host_tables", "omc_host_ms_table", "omc_last_error", "omc_destroy"]
+
+
+class OmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"omc error {code}: {msg}")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("n_elem", C.c_int), ("Z", C.POINTER(C.c_int)), ("A", C.POINTER(C.c_double)),
+                ("w_mass", C.POINTER(C.c_double)), ("I_eV", C.c_double),
+                ("rho_nominal", C.c_double)]
+
+
+class Source(C.Structure):
+    _fields_ = [("particle", C.c_int), ("n_bins", C.c_int), ("edges", C.POINTER(C.c_double)),
+                ("weights", C.POINTER(C.c_double)), ("mono_E", C.c_double),
+                ("geometry", C.c_int), ("ssd", C.c_double), ("z_field", C.c_double),
+                ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("sx", C.c_double), ("sy", C.c_double), ("gantry_deg", C.c_double),
+                ("iso_x", C.c_double), ("iso_z", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("Eabs_e", C.c_double), ("Eabs_g", C.c_double), ("Wcc", C.c_double),
+                ("kc", C.c_double), ("dmax_s", C.c_double), ("f_E", C.c_double),
+                ("n_batches", C.c_int), ("parity_fp64", C.c_int), ("kerma_mode", C.c_int),
+                ("csda_mode", C.c_int), ("block_size", C.c_int), ("blocks_per_cu", C.c_int),
+                ("chunk_histories", C.c_int), ("queue_factor", C.c_int), ("timing", C.c_int)]
+
+
+COUNTER_INT = ["ph_flights", "ph_fictitious", "ph_compton", "ph_photo", "ph_pair", "ph_cutoff",
+               "ph_escaped", "el_steps", "el_hard_cand", "el_hard_fict", "el_moller", "el_brems",
+               "el_absorbed", "el_escaped", "el_boundary", "el_hinge_trunc", "pos_annihil",
+               "push_ph", "push_el", "src_miss"]
+COUNTER_EXTRA = ["watchdog"]
+COUNTER_FP = ["E_incident", "E_deposited", "E_escaped", "E_pair_rest", "E_annih_rest"]
+
+
+class Counters(C.Structure):
+    _fields_ = ([(n, C.c_uint64) for n in COUNTER_INT + COUNTER_EXTRA]
+                + [(n, C.c_double) for n in COUNTER_FP]
+                + [("queue_hwm_ph", C.c_uint64), ("queue_hwm_el", C.c_uint64),
+                   ("iterations", C.c_uint32)])
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Timing(C.Structure):
+    _fields_ = [("launches", C.c_uint32 * 4), ("total_ms", C.c_double * 4), ("run_ms", C.c_double)]
+
+    def as_dict(self):
+        names = ["source", "photon", "electron", "fold"]
+        return {"launches": dict(zip(names, list(self.launches))),
+                "total_ms": dict(zip(names, list(self.total_ms))), "run_ms": self.run_ms}
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        L.omc_default_params.argtypes = [C.POINTER(Params)]
+        L.omc_default_params.restype = None
+        L.omc_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                 C.c_double, C.POINTER(C.c_float), C.POINTER(C.c_uint8),
+                                 C.POINTER(Material), C.c_int]
+        L.omc_set_source.argtypes = [vp, C.POINTER(Source)]
+        L.omc_set_params.argtypes = [vp, C.POINTER(Params)]
+        L.omc_run.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, dp, dp]
+        L.omc_run_device.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp]
+        L.omc_get_counters.argtypes = [vp, C.POINTER(Counters)]
+        L.omc_get_timing.argtypes = [vp, C.POINTER(Timing)]
+        L.omc_debug_philox.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                       C.POINTER(C.c_uint32)]
+        L.omc_host_tables.argtypes = [C.POINTER(Material), C.c_double, C.c_double, dp]
+        L.omc_host_ms_table.argtypes = [dp]
+        L.omc_last_error.argtypes = [vp]
+        L.omc_last_error.restype = C.c_char_p
+        L.omc_destroy.argtypes = [vp]
+        L.omc_destroy.restype = None
+        for name in EXPORTS:
+            if name not in ("omc_default_params", "omc_last_error", "omc_destroy"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != OMC_OK:
+        msg = lib().omc_last_error(ctx)
+        raise OmcError(rc, msg.decode() if msg else "")
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class _MaterialHolder:
+    def __init__(self, spec):
+        self.Z = np.ascontiguousarray(spec["Z"], dtype=np.int32)
+        self.A = np.ascontiguousarray(spec["A"], dtype=np.float64)
+        self.w = np.ascontiguousarray(spec["w"], dtype=np.float64)
+        self.struct = Material(len(self.Z), self.Z.ctypes.data_as(C.POINTER(C.c_int)),
+                               _dptr(self.A), _dptr(self.w), float(spec["I_eV"]),
+                               float(spec["rho_nom"]))
+
+
+def default_params():
+    p = Params()
+    lib().omc_default_params(C.byref(p))
+    return p
+
+
+class Engine:
+    """One phantom on the current HIP device (see omc_create)."""
+
+    def __init__(self, phantom):
+        self.shape = tuple(phantom["shape"])
+        nz, ny, nx = self.shape
+        dz, dy, dx = phantom["voxel"]
+        dens = np.ascontiguousarray(phantom["density"], dtype=np.float32).ravel()
+        mat = np.ascontiguousarray(phantom["material"], dtype=np.uint8).ravel()
+        holders = [_MaterialHolder(m) for m in phantom["materials"]]
+        arr = (Material * len(holders))(*[h.struct for h in holders])
+        h = C.c_void_p()
+        rc = lib().omc_create(C.byref(h), nx, ny, nz, dx, dy, dz,
+                              dens.ctypes.data_as(C.POINTER(C.c_float)),
+                              mat.ctypes.data_as(C.POINTER(C.c_uint8)), arr, len(holders))
+        _check(rc, None)
+        self._h = h
+        self.params = default_params()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().omc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_source(self, src):
+        nb = int(src.get("n_bins", 0) or 0)
+        edges = np.ascontiguousarray(src.get("edges", np.zeros(1)), dtype=np.float64)
+        weights = np.ascontiguousarray(src.get("weights", np.zeros(1)), dtype=np.float64)
+        s = Source(int(src["particle"]), nb, _dptr(edges), _dptr(weights),
+                   float(src.get("mono_E", 0.0)), int(src["geometry"]),
+                   float(src.get("ssd", 100.0)), float(src.get("z_field", 0.0)),
+                   float(src["fx"]), float(src["fy"]), float(src["cx"]), float(src["cy"]),
+                   float(src.get("sx", src["cx"])), float(src.get("sy", src["cy"])),
+                   float(src.get("gantry_deg", 0.0)), float(src.get("iso_x", 0.0)),
+                   float(src.get("iso_z", 0.0)))
+        _check(lib().omc_set_source(self._h, C.byref(s)), self._h)
+
+    def set_params(self, **kw):
+        p = Params.from_buffer_copy(self.params)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        _check(lib().omc_set_params(self._h, C.byref(p)), self._h)
+        self.params = p
+
+    def run(self, n, seed=1, h0=0, check=True):
+        nvox = int(np.prod(self.shape))
+        dose = np.zeros(nvox)
+        dose2 = np.zeros(nvox)
+        rc = lib().omc_run(self._h, int(n), int(seed), int(h0), _dptr(dose), _dptr(dose2))
+        if check:
+            _check(rc, self._h)
+        return dose.reshape(self.shape), dose2.reshape(self.shape)
+
+    def run_device(self, n, seed, h0, dose, dose2, stream=None):
+        """dose, dose2: float64 CUDA tensors with nvox elements; stream: a
+        torch.cuda.Stream or None for the current stream."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        assert dose.dtype == torch.float64 and dose.is_cuda and dose.is_contiguous()
+        assert dose2.dtype == torch.float64 and dose2.is_cuda and dose2.is_contiguous()
+        assert dose.numel() == dose2.numel() == int(np.prod(self.shape))
+        rc = lib().omc_run_device(self._h, int(n), int(seed), int(h0), C.c_void_p(dose.data_ptr()),
+                                  C.c_void_p(dose2.data_ptr()), C.c_void_p(stream.cuda_stream))
+        _check(rc, self._h)
+
+    def counters(self):
+        c = Counters()
+        _check(lib().omc_get_counters(self._h, C.byref(c)), self._h)
+        return c.as_dict()
+
+    def timing(self):
+        t = Timing()
+        _check(lib().omc_get_timing(self._h, C.byref(t)), self._h)
+        return t.as_dict()
+
+
+def debug_philox(seed, h, q, n0, nblocks):
+    out = np.zeros(4 * nblocks, dtype=np.uint32)
+    _check(lib().omc_debug_philox(seed, h, q, n0, nblocks,
+                                  out.ctypes.data_as(C.POINTER(C.c_uint32))))
+    return out
+
+
+def host_tables(spec, Wcc=0.05, kc=0.2):
+    m = _MaterialHolder(spec)
+    out = np.zeros(len(TABLE_ROWS) * NE)
+    _check(lib().omc_host_tables(C.byref(m.struct), Wcc, kc, _dptr(out)))
+    out = out.reshape(len(TABLE_ROWS), NE)
+    return {n: out[i] for i, n in enumerate(TABLE_ROWS)}
+
+
+def host_ms_table():
+    out = np.zeros(NA)
+    _check(lib().omc_host_ms_table(_dptr(out)))
+    return out

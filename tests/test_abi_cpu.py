@@ -1,0 +1,125 @@
+"""CPU-only checks of the HIP library's host side: it loads and exports every
+symbol include/omc.h declares, it validates arguments before touching a device,
+and its own closed-form table builder (independent of the oracle's) agrees with
+the oracle's tables. No kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def omc():
+    from paper_1503_01722_amd import omc
+    omc.lib()
+    return omc
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "omc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(omc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(omc):
+    names = header_functions()
+    assert len(names) >= 13
+    L = omc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(omc.EXPORTS)
+
+
+def test_default_params(omc):
+    p = omc.default_params()
+    assert (p.Eabs_e, p.Eabs_g, p.Wcc, p.kc, p.dmax_s, p.f_E) == (0.2, 0.05, 0.05, 0.2, 0.5, 0.25)
+    assert p.n_batches == 10 and p.parity_fp64 == 0 and p.block_size == 256
+
+
+def _create(omc, dens, mat, mats, dims=(4, 4, 4), h=(0.5, 0.5, 0.5)):
+    holders = [omc._MaterialHolder(m) for m in mats]
+    arr = (omc.Material * max(1, len(holders)))(*[x.struct for x in holders])
+    ctx = C.c_void_p()
+    rc = omc.lib().omc_create(C.byref(ctx), *dims, *h,
+                              np.ascontiguousarray(dens, np.float32).ctypes.data_as(
+                                  C.POINTER(C.c_float)),
+                              np.ascontiguousarray(mat, np.uint8).ctypes.data_as(
+                                  C.POINTER(C.c_uint8)), arr, len(holders))
+    return rc, ctx
+
+
+def gpu_present():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def test_argument_validation(omc, W):
+    good_d = np.ones(64, np.float32)
+    good_m = np.zeros(64, np.uint8)
+    mats = [W.WATER]
+    cases = [
+        (good_d, good_m, mats, (0, 4, 4), (0.5, 0.5, 0.5)),          # empty dimension
+        (good_d, good_m, mats, (4, 4, 2000), (0.5, 0.5, 0.5)),       # too large
+        (good_d, good_m, mats, (4, 4, 4), (0.5, -1.0, 0.5)),         # negative voxel
+        (np.where(np.arange(64) == 5, np.nan, 1).astype(np.float32), good_m, mats, (4, 4, 4),
+         (0.5, 0.5, 0.5)),                                           # NaN density
+        (np.where(np.arange(64) == 5, 0, 1).astype(np.float32), good_m, mats, (4, 4, 4),
+         (0.5, 0.5, 0.5)),                                           # zero density
+        (good_d, np.full(64, 3, np.uint8), mats, (4, 4, 4), (0.5, 0.5, 0.5)),  # bad material id
+        (good_d, good_m, [], (4, 4, 4), (0.5, 0.5, 0.5)),            # no materials
+    ]
+    for d, m, ms, dims, h in cases:
+        rc, ctx = _create(omc, d, m, ms, dims, h)
+        assert rc == omc.OMC_EINVAL and not ctx.value
+        assert omc.lib().omc_last_error(None)
+    bad_mat = dict(W.WATER, I_eV=-1.0)
+    rc, _ = _create(omc, good_d, good_m, [bad_mat])
+    assert rc == omc.OMC_EINVAL
+    # NULL context everywhere
+    L = omc.lib()
+    assert L.omc_set_source(None, None) == omc.OMC_EINVAL
+    assert L.omc_set_params(None, None) == omc.OMC_EINVAL
+    assert L.omc_run(None, 10, 1, 0, None, None) == omc.OMC_EINVAL
+    assert L.omc_get_counters(None, None) == omc.OMC_EINVAL
+    L.omc_destroy(None)
+    if not gpu_present():
+        rc, ctx = _create(omc, good_d, good_m, mats)
+        assert rc == omc.OMC_EDEVICE and not ctx.value
+        out = np.zeros(4, np.uint32)
+        assert L.omc_debug_philox(1, 0, 0, 0, 1, out.ctypes.data_as(
+            C.POINTER(C.c_uint32))) == omc.OMC_EDEVICE
+
+
+@pytest.mark.parametrize("name", ["WATER", "LUNG", "BONE"])
+def test_host_tables_match_oracle(omc, orc, W, name):
+    """Two independent implementations of the closed forms agree to 1e-12."""
+    spec = getattr(W, name)
+    for Wcc, kc in ((0.05, 0.2), (0.2, 0.05)):
+        a = omc.host_tables(spec, Wcc, kc)
+        b = orc.mat_tables(spec, Wcc, kc)
+        for k in omc.TABLE_ROWS:
+            np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=0, err_msg=k)
+
+
+def test_host_ms_table_matches_oracle(omc, orc):
+    a, b = omc.host_ms_table(), orc.ms_table()
+    # m1(A) = 1 - 1/(3A) + ... loses log10(A) digits to cancellation where A is
+    # large (x near 8, A near 1000), so two bisections stop up to ~1e-10 apart there
+    np.testing.assert_allclose(a[:480], b[:480], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(a, b, rtol=1e-9, atol=0)
+
+
+def test_host_tables_spot_values(omc, W):
+    t = omc.host_tables(W.WATER)
+    E = np.exp2(np.log2(0.01) + np.arange(512) * np.log2(2000.0) / 511)
+    i = int(np.argmin(abs(E - 1.0)))
+    assert t["muC"][i] == pytest.approx(0.0707 * (1 + 0.0), rel=0.02)
+    assert np.all(np.diff(t["R"]) > 0) and t["R"][0] == 0.0
+    assert np.all(t["sigHat"] == np.maximum.accumulate(t["sigM"] + t["sigB"]))
