@@ -151,6 +151,13 @@ void orc_sample_source(const orc_problem* p, uint32_t seed, uint32_t h0, uint32_
 int orc_first_interaction(const orc_problem* p, uint32_t seed, uint32_t h0, uint32_t n,
                           double* pos, int* type, uint64_t* n_fict);
 
+/* Debugging aid: transport history h alone, recording 12 doubles per electron
+ * step {code, id_lo, id_hi, stream position, x, y, z, u, v, w, E, voxel}
+ * after the step (code 16 + limiter + 8 * crossed, 64 = absorbed). Not
+ * thread-safe. */
+int orc_trace(const orc_problem* p, uint32_t seed, uint32_t h, double* out, uint32_t cap,
+              uint32_t* n_out);
+
 /* Full run of histories h0..h0+N-1. dose, dose2: nx*ny*nz, MeV/g per history
  * and sum over batches of the squared batch dose. Returns 0 or <0 on error. */
 int orc_run(const orc_problem* p, uint64_t N, uint32_t seed, uint32_t h0, int nthreads,

@@ -133,6 +133,9 @@ def lib():
                                             C.c_uint32, dp, C.POINTER(C.c_int),
                                             C.POINTER(C.c_uint64)]
         L.orc_first_interaction.restype = C.c_int
+        L.orc_trace.argtypes = [C.POINTER(Problem), C.c_uint32, C.c_uint32, dp, C.c_uint32,
+                                C.POINTER(C.c_uint32)]
+        L.orc_trace.restype = C.c_int
         L.orc_run.argtypes = [C.POINTER(Problem), C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                               dp, dp, C.POINTER(Counters)]
         L.orc_run.restype = C.c_int
@@ -253,6 +256,16 @@ def run(phantom, source, n, seed=1, h0=0, params=None, threads=None):
         raise ValueError("oracle rejected the problem (rc=%d)" % rc)
     shape = tuple(phantom["shape"])
     return dose.reshape(shape), dose2.reshape(shape), cnt.as_dict()
+
+
+def trace(phantom, source, h, seed=1, params=None, cap=1 << 16):
+    """Electron step records of history h alone (see orc_trace)."""
+    pr = _ProblemHolder(phantom, source, params)
+    out = np.zeros(12 * cap)
+    n = C.c_uint32(0)
+    if lib().orc_trace(C.byref(pr.struct), seed, h, _dptr(out), cap, C.byref(n)) != 0:
+        raise ValueError("oracle rejected the problem")
+    return out[: 12 * n.value].reshape(n.value, 12)
 
 
 def first_interaction(phantom, source, n, seed=1, h0=0, params=None):

@@ -12,7 +12,8 @@
  *             kinetic energy split uniformly).
  *   electrons Sec. 2.1: Class II condensed history; step
  *             d = min(d_vox, d_maxs, d_maxe, d_abs, d_event); random hinge with
- *             the multiple-scattering deflection; CSDA loss from the range table
+ *             the multiple-scattering deflection (skipped for a step that ends
+ *             on a face within the boundary skin); CSDA loss from the range table
  *             deposited in the voxel of the step; hard event accepted with the
  *             Woodcock ratio; Moller or bremsstrahlung; positrons annihilate
  *             into two back-to-back photons at the end of the track.
@@ -110,6 +111,7 @@ typedef struct {
     double muhat[ORC_NE];
     double log2A[ORC_NA];
     double* cdf;
+    double skin; /* boundary skin depth, cm */
 } ctx_t;
 
 typedef struct {
@@ -467,6 +469,30 @@ static void hard_event(const ctx_t* C, part_t* p, const orc_mat_tables* T, doubl
     p->nmfp = -log(rng_u(&p->rng));
 }
 
+/* Step trace of one history (debugging aid, single-threaded use only). */
+static double* g_trace = NULL;
+static uint32_t g_trace_cap = 0, g_trace_n = 0;
+
+static void trace_step(const ctx_t* C, const part_t* p, int code)
+{
+    if (!g_trace) return;
+    if (g_trace_n < g_trace_cap) {
+        double* r = g_trace + 12 * (size_t)g_trace_n;
+        r[0] = code;
+        r[1] = (double)(uint32_t)p->rng.q;
+        r[2] = (double)(uint32_t)(p->rng.q >> 32);
+        r[3] = 4.0 * (double)p->rng.n - (double)(4 - p->rng.nw);
+        for (int a = 0; a < 3; ++a) {
+            r[4 + a] = p->x[a];
+            r[7 + a] = p->d[a];
+        }
+        r[10] = p->E;
+        r[11] = (double)p->iv[0] + 1024.0 * ((double)p->iv[1] + 1024.0 * (double)p->iv[2]);
+    }
+    g_trace_n++;
+    (void)C;
+}
+
 static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
 {
     const orc_problem* P = C->P;
@@ -475,6 +501,7 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
         if (p->E <= P->Eabs_e) {
             deposit(t, v, p->E);
             t->c.el_absorbed++;
+            trace_step(C, p, 64);
             if (p->type == PT_POSITRON) annihilate(C, st, t, &p->rng, p->x, p->iv);
             return;
         }
@@ -505,7 +532,9 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
         int crossed = 0, cax = ax;
         if (d > 0.0) {
             double s;
-            if (P->csda_mode) {
+            if (P->csda_mode || (lim == LIM_VOX && d < C->skin)) {
+                /* straight line; inside the boundary skin the hinge deflection
+                 * is skipped and the step ends on the face */
                 for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + d * p->d[a];
                 s = d;
                 if (lim == LIM_VOX) crossed = 1;
@@ -554,6 +583,7 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
             p->x[a] = up ? (double)(p->iv[a] + 1) * C->h[a] : (double)p->iv[a] * C->h[a];
             p->iv[a] += up ? 1 : -1;
             t->c.el_boundary++;
+            trace_step(C, p, 16 + lim + 8 * crossed);
             if (p->iv[a] < 0 || p->iv[a] >= C->n[a]) {
                 t->c.E_escaped += p->E;
                 t->c.el_escaped++;
@@ -562,6 +592,7 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
             continue;
         }
         if (lim == LIM_EVENT) hard_event(C, p, T, shm, st, t);
+        trace_step(C, p, 16 + lim);
     }
 }
 
@@ -676,6 +707,11 @@ static int ctx_init(ctx_t* C, const orc_problem* P, uint32_t seed)
     C->h[1] = P->dy;
     C->h[2] = P->dz;
     C->nvox = (size_t)P->nx * (size_t)P->ny * (size_t)P->nz;
+    /* A step that reaches a voxel face within this distance is taken without
+     * the hinge deflection, as in the boundary-crossing algorithm that comes
+     * with the random hinge (Kawrakow 2000). Without it, steps that end just
+     * short of a face shrink geometrically toward it. */
+    C->skin = 1e-3 * fmin(P->dx, fmin(P->dy, P->dz));
     C->rho = (double*)malloc(C->nvox * sizeof(double));
     C->tab = (orc_mat_tables*)calloc((size_t)P->n_mats, sizeof(orc_mat_tables));
     C->Rabs = (double*)calloc((size_t)P->n_mats, sizeof(double));
@@ -813,6 +849,30 @@ int orc_run(const orc_problem* P, uint64_t N, uint32_t seed, uint32_t h0, int nt
 }
 
 /* --- test entry points ------------------------------------------------------------ */
+
+int orc_trace(const orc_problem* P, uint32_t seed, uint32_t h, double* out, uint32_t cap,
+              uint32_t* n_out)
+{
+    ctx_t C;
+    if (ctx_init(&C, P, seed) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    tally_t t;
+    t.grid = (double*)calloc(C.nvox, sizeof(double));
+    memset(&t.c, 0, sizeof t.c);
+    stack_t st = {NULL, 0, 0};
+    g_trace = out;
+    g_trace_cap = cap;
+    g_trace_n = 0;
+    run_history(&C, h, &st, &t);
+    *n_out = g_trace_n < cap ? g_trace_n : cap;
+    g_trace = NULL;
+    free(st.a);
+    free(t.grid);
+    ctx_free(&C);
+    return 0;
+}
 
 int orc_first_interaction(const orc_problem* P, uint32_t seed, uint32_t h0, uint32_t n,
                           double* pos, int* type, uint64_t* n_fict)
