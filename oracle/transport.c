@@ -575,6 +575,11 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
             p->E = Tend;
         } else if (lim == LIM_VOX) {
             crossed = 1; /* zero-length step on a face: only the index moves */
+        } else if (lim == LIM_ABS) {
+            /* no range left above the absorption energy (T within rounding of
+             * E_abs): the track ends; the remainder is deposited here */
+            deposit(t, v, T0 - P->Eabs_e);
+            p->E = P->Eabs_e;
         }
 
         if (crossed) {
