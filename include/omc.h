@@ -110,6 +110,7 @@ typedef struct {
     double E_incident, E_deposited, E_escaped, E_pair_rest, E_annih_rest;
     uint64_t queue_hwm_ph, queue_hwm_el; /* largest queue occupancy seen */
     uint32_t iterations;                 /* photon/electron generations launched */
+    uint32_t max_steps;                  /* most steps taken by one particle */
 } omc_counters;
 
 /* Per-kernel timing of the last run (params.timing == 1), HIP events on the
@@ -157,6 +158,14 @@ int omc_get_timing(const omc_ctx* ctx, omc_timing* out);
  * (host memory, caller-owned). */
 int omc_debug_philox(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
                      uint32_t* out);
+
+/* Debugging aid: transport history h alone (stream key (seed, h)) and record
+ * every electron step: out receives up to max_records records of 12 doubles
+ * {code, id_lo, id_hi, stream position, x, y, z, u, v, w, E, voxel} taken after
+ * the step (code 16 + limiter + 8 * crossed, 64 = absorbed); *n_records gets
+ * the number written. Records of one particle are in step order. */
+int omc_debug_trace(omc_ctx* ctx, uint32_t seed, uint32_t h, double* out, uint32_t max_records,
+                    uint32_t* n_records);
 
 /* Host-only (no device needed): the engine's own table builder. out receives
  * OMC_TABLE_ROWS x OMC_NE doubles in the row order muC, muPE, muPair, muTot,

@@ -191,6 +191,7 @@ struct Particle {
 struct LaneStats {
     uint32_t c[kNumCounters];
     double e_dep, e_esc, e_inc;
+    uint32_t max_steps;  // longest particle handled by the lane
 };
 
 __device__ __forceinline__ uint32_t pack_vox(int ix, int iy, int iz)
@@ -300,6 +301,28 @@ struct Ctx {
         return Math<R>::exp2(lerp(msA[i], msA[i + 1], f));
     }
 
+    // ---- step trace of one history: code, particle id, stream position,
+    // position, direction, energy, packed voxel (after the step)
+    __device__ __forceinline__ void trace(const Particle<R>& p, int code) const
+    {
+        if (!a.trace.on || p.h != a.trace.h) return;
+        const uint32_t k = atomicAdd(a.trace.n, 1u);
+        if (k >= a.trace.cap) return;
+        double* r = a.trace.buf + size_t(k) * kTraceWords;
+        r[0] = code;
+        r[1] = p.rng.q0;
+        r[2] = p.rng.q1;
+        r[3] = 4.0 * double(p.rng.n) - double(p.rng.left);
+        r[4] = double(p.x);
+        r[5] = double(p.y);
+        r[6] = double(p.z);
+        r[7] = double(p.u);
+        r[8] = double(p.v);
+        r[9] = double(p.w);
+        r[10] = double(p.E);
+        r[11] = double(p.ix) + 1024.0 * (double(p.iy) + 1024.0 * double(p.iz));
+    }
+
     // ---- geometry
     __device__ __forceinline__ R coord(R x, R h, R ih) const
     {
@@ -312,9 +335,10 @@ struct Ctx {
         const R fx = coord(p.x, a.ph.hx, a.ph.ihx);
         const R fy = coord(p.y, a.ph.hy, a.ph.ihy);
         const R fz = coord(p.z, a.ph.hz, a.ph.ihz);
-        if (fx < R(0) || fx >= R(a.ph.nx)) return false;
-        if (fy < R(0) || fy >= R(a.ph.ny)) return false;
-        if (fz < R(0) || fz >= R(a.ph.nz)) return false;
+        // written so that a NaN coordinate counts as outside
+        if (!(fx >= R(0) && fx < R(a.ph.nx))) return false;
+        if (!(fy >= R(0) && fy < R(a.ph.ny))) return false;
+        if (!(fz >= R(0) && fz < R(a.ph.nz))) return false;
         p.ix = int(fx);
         p.iy = int(fy);
         p.iz = int(fz);
@@ -627,6 +651,7 @@ struct Ctx {
         if (p.E <= a.prm.Eabs_e) {
             deposit(p, vx, double(p.E));
             st.c[C_EL_ABSORBED] += 1;
+            trace(p, 64);
             if (p.type == PT_POSITRON) annihilate(p);
             return false;
         }
@@ -661,7 +686,9 @@ struct Ctx {
         int cax = ax;
         if (d > R(0)) {
             R s;
-            if (csda) {
+            // straight line in CSDA mode, and inside the boundary skin where the
+            // hinge deflection is skipped so that the step ends on the face
+            if (csda || (lim == VOX && d < a.prm.skin)) {
                 p.x = p.x + d * p.u;
                 p.y = p.y + d * p.v;
                 p.z = p.z + d * p.w;
@@ -682,7 +709,8 @@ struct Ctx {
                 const R k1 = lerp(K1[m * kTabNE + i2], K1[m * kTabNE + i2 + 1], f2);
                 const R A = screening(d * rho * k1);
                 const R um = p.rng.template uniform<R>();
-                const R omc = Math<R>::div(R(2) * A * um, R(1) + A - um);
+                R omc = Math<R>::div(R(2) * A * um, R(1) + A - um);
+                if (omc > R(2)) omc = R(2);  // rounding of the fast reciprocal (FP32)
                 R sf, cf;
                 Math<R>::sincos_turns(p.rng.template uniform<R>(), sf, cf);
                 rotate(p.u, p.v, p.w, R(1) - omc, Math<R>::sqrt(omc * (R(2) - omc)), cf, sf);
@@ -713,6 +741,11 @@ struct Ctx {
             p.E = Tend;
         } else if (lim == VOX) {
             crossed = true;  // zero-length step on a face: only the index moves
+        } else if (lim == ABS) {
+            // no range left above the absorption energy (T within rounding of
+            // E_abs): the track ends; the remainder is deposited here
+            deposit(p, vx, double(T0) - double(a.prm.Eabs_e));
+            p.E = a.prm.Eabs_e;
         }
 
         if (crossed) {
@@ -735,6 +768,7 @@ struct Ctx {
                 out = p.iz < 0 || p.iz >= a.ph.nz;
             }
             st.c[C_EL_BOUNDARY] += 1;
+            trace(p, 16 + lim + 8 * int(crossed));
             if (out) {
                 st.e_esc += double(p.E);
                 st.c[C_EL_ESCAPED] += 1;
@@ -743,6 +777,7 @@ struct Ctx {
             return true;
         }
         if (lim == EVENT) hard_event(p, m, shm, vx);
+        trace(p, 16 + lim);
         return true;
     }
 };
@@ -777,6 +812,10 @@ __device__ __forceinline__ void flush_stats(const StatsView& sv, const LaneStats
     wave_flush_f64(&sv.energies[EN_DEPOSITED], st.e_dep);
     wave_flush_f64(&sv.energies[EN_ESCAPED], st.e_esc);
     wave_flush_f64(&sv.energies[EN_INCIDENT], st.e_inc);
+    uint32_t m = st.max_steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, uint32_t(__shfl_xor(m, off)));
+    if (lane_id() == 0 && m) atomicMax(sv.max_steps, m);
 }
 
 __device__ __forceinline__ uint32_t batch_of(const TallyView& t, uint32_t h)
@@ -849,11 +888,13 @@ __device__ __forceinline__ void transport_loop(const KernelArgs<R>& a, const Ctx
         if (__ballot(alive) == 0) break;
         if (alive) {
             alive = kPhoton ? cx.photon_step(p) : cx.electron_step(p);
-            if (alive && ++steps >= kMaxSteps) {
+            ++steps;
+            if (alive && steps >= kMaxSteps) {
                 cx.deposit(p, cx.lin(p.ix, p.iy, p.iz), double(p.E));
                 cx.st.c[C_WATCHDOG] += 1;
                 alive = false;
             }
+            if (!alive && steps > cx.st.max_steps) cx.st.max_steps = steps;
         }
     }
 }

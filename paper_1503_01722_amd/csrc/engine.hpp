@@ -91,6 +91,7 @@ struct TableView {
 template <typename R>
 struct ParamView {
     R Eabs_e, Eabs_g, Wcc, kc, dmax_s, one_minus_fE;
+    R skin;  // boundary skin depth: 1e-3 of the smallest voxel side
     int kerma, csda;
 };
 
@@ -106,6 +107,7 @@ struct StatsView {
     unsigned long long* counters;  // [kNumCounters]
     double* energies;              // [kNumEnergies]
     uint32_t* overflow;            // set to 1 when a push found its queue full
+    uint32_t* max_steps;           // longest particle (steps) of the run
 };
 
 template <typename R>
@@ -121,6 +123,16 @@ struct SourceView {
     R cg, sg, iso_x, iso_z;  // cos/sin of the gantry angle (host FP64)
 };
 
+// Step trace of one history (debugging aid): 12 doubles per electron step.
+struct TraceView {
+    double* buf;
+    uint32_t* n;
+    uint32_t cap;
+    uint32_t h;
+    int on;
+};
+constexpr int kTraceWords = 12;
+
 template <typename R>
 struct KernelArgs {
     PhantomView<R> ph;
@@ -132,6 +144,7 @@ struct KernelArgs {
     TallyView tally;
     StatsView stats;
     SourceView<R> src;
+    TraceView trace;
     uint32_t seed;
     uint32_t src_begin;   // first history of this source chunk (relative to h0)
     uint32_t src_count;

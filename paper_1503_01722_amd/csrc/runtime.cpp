@@ -93,6 +93,7 @@ struct omc_ctx {
 
     omc_counters last{};
     omc_timing timing{};
+    omc::TraceView trace{};
     std::string err;
 };
 
@@ -420,10 +421,13 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     a.tab.XINV = R(double(omc::kNA - 1) / (omc::kXHi - omc::kXLo));
     a.tab.ELo = R(omc::kELo);
     a.tab.EHi = R(omc::kEHi);
-    a.prm = {R(P.Eabs_e), R(P.Eabs_g), R(P.Wcc), R(P.kc), R(P.dmax_s), R(1.0 - P.f_E),
+    // boundary skin (Kawrakow 2000): a voxel-limited step shorter than this is
+    // taken straight to the face without the hinge deflection
+    const double skin = 1e-3 * std::fmin(c->dx, std::fmin(c->dy, c->dz));
+    a.prm = {R(P.Eabs_e), R(P.Eabs_g), R(P.Wcc), R(P.kc), R(P.dmax_s), R(1.0 - P.f_E), R(skin),
              P.kerma_mode, P.csda_mode};
     a.tally = {c->d_grid, c->nvox, N, h0, B};
-    a.stats = {c->d_counters, c->d_energies, c->d_ctrl + 8};
+    a.stats = {c->d_counters, c->d_energies, c->d_ctrl + 8, c->d_ctrl + 9};
     const omc_source& sr = c->src;
     a.src.cdf = c->d_cdf;
     a.src.edges = T.edges;
@@ -445,6 +449,7 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     a.src.sg = R(std::sin(gr));
     a.src.iso_x = R(sr.iso_x);
     a.src.iso_z = R(sr.iso_z);
+    a.trace = c->trace;
     a.seed = seed;
     a.chunk = 64;
 
@@ -522,6 +527,8 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     tm.end();
     unsigned long long cnts[omc::kNumCounters];
     double en[omc::kNumEnergies];
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              s));
     HIP_TRY(c, hipMemcpyAsync(cnts, c->d_counters, sizeof cnts, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(en, c->d_energies, sizeof en, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -533,6 +540,7 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     L.E_pair_rest = double(L.ph_pair) * 2.0 * omc::kMC2;
     L.E_annih_rest = double(L.pos_annihil) * 2.0 * omc::kMC2;
     L.iterations = iters;
+    L.max_steps = c->h_ctrl[9];
     const double lhs = L.E_incident + L.E_annih_rest - L.E_pair_rest;
     const double rhs = L.E_deposited + L.E_escaped;
     if (!std::isfinite(lhs) || !std::isfinite(rhs) || std::fabs(lhs - rhs) > 1e-9 * std::fabs(lhs))
@@ -775,6 +783,44 @@ int omc_debug_philox(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_
             hipSuccess)
         rc = fail(nullptr, OMC_EDEVICE, "Philox debug kernel failed");
     (void)hipFree(d);
+    return rc;
+}
+
+int omc_debug_trace(omc_ctx* c, uint32_t seed, uint32_t h, double* out, uint32_t max_records,
+                    uint32_t* n_records)
+{
+    if (check_ctx(c) || !out || !n_records || max_records == 0 || max_records > (1u << 24))
+        return fail(c, OMC_EINVAL, "invalid trace arguments");
+    if (!c->has_source) return fail(c, OMC_ESTATE, "omc_set_source must be called first");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t bytes = size_t(max_records) * omc::kTraceWords * sizeof(double);
+    double* d_buf = nullptr;
+    uint32_t* d_n = nullptr;
+    double *d_dose = nullptr, *d_dose2 = nullptr;
+    int rc = OMC_OK;
+    if (hipMalloc(&d_buf, bytes) != hipSuccess || hipMalloc(&d_n, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&d_dose, c->nvox * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_dose2, c->nvox * sizeof(double)) != hipSuccess) {
+        rc = fail(c, OMC_ENOMEM, "hipMalloc failed for the trace");
+    } else if (hipMemset(d_n, 0, sizeof(uint32_t)) != hipSuccess) {
+        rc = fail(c, OMC_EDEVICE, "hipMemset failed");
+    } else {
+        c->trace = omc::TraceView{d_buf, d_n, max_records, h, 1};
+        rc = c->prm.parity_fp64 ? run_impl<double>(c, 1, seed, h, d_dose, d_dose2, nullptr)
+                                : run_impl<float>(c, 1, seed, h, d_dose, d_dose2, nullptr);
+        c->trace = omc::TraceView{};
+        uint32_t n = 0;
+        if (rc == OMC_OK &&
+            (hipMemcpy(&n, d_n, sizeof n, hipMemcpyDeviceToHost) != hipSuccess ||
+             hipMemcpy(out, d_buf, size_t(std::min(n, max_records)) * omc::kTraceWords *
+                                       sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
+            rc = fail(c, OMC_EDEVICE, "trace readback failed");
+        *n_records = std::min(n, max_records);
+    }
+    dfree(d_buf);
+    dfree(d_n);
+    dfree(d_dose);
+    dfree(d_dose2);
     return rc;
 }
 

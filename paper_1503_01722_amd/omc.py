@@ -20,7 +20,7 @@ NA = 512
 TABLE_ROWS = ["muC", "muPE", "muPair", "muTot", "Scol", "Srad", "R", "sigM", "sigB", "sigHat",
               "K1"]
 EXPORTS = ["omc_default_params", "omc_create", "omc_set_source", "omc_set_params", "omc_run",
-           "omc_run_device", "omc_get_counters", "omc_get_timing", "omc_debug_philox",
+           "omc_run_device", "omc_get_counters", "omc_get_timing", "omc_debug_philox", "omc_debug_trace",
            "omc_host_tables", "omc_host_ms_table", "omc_last_error", "omc_destroy"]
 
 
@@ -65,7 +65,7 @@ class Counters(C.Structure):
     _fields_ = ([(n, C.c_uint64) for n in COUNTER_INT + COUNTER_EXTRA]
                 + [(n, C.c_double) for n in COUNTER_FP]
                 + [("queue_hwm_ph", C.c_uint64), ("queue_hwm_el", C.c_uint64),
-                   ("iterations", C.c_uint32)])
+                   ("iterations", C.c_uint32), ("max_steps", C.c_uint32)])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -90,6 +90,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
                                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch ships its own HIP runtime with the same soname; loading torch
+        # first makes this library bind to it, so that device pointers and
+        # streams from torch are valid here (one runtime per process)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         dp = C.POINTER(C.c_double)
@@ -106,6 +113,8 @@ def lib():
         L.omc_get_timing.argtypes = [vp, C.POINTER(Timing)]
         L.omc_debug_philox.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
                                        C.POINTER(C.c_uint32)]
+        L.omc_debug_trace.argtypes = [vp, C.c_uint32, C.c_uint32, dp, C.c_uint32,
+                                      C.POINTER(C.c_uint32)]
         L.omc_host_tables.argtypes = [C.POINTER(Material), C.c_double, C.c_double, dp]
         L.omc_host_ms_table.argtypes = [dp]
         L.omc_last_error.argtypes = [vp]
@@ -216,6 +225,14 @@ class Engine:
         rc = lib().omc_run_device(self._h, int(n), int(seed), int(h0), C.c_void_p(dose.data_ptr()),
                                   C.c_void_p(dose2.data_ptr()), C.c_void_p(stream.cuda_stream))
         _check(rc, self._h)
+
+    def trace(self, h, seed=1, max_records=1 << 16):
+        """Step records of history h alone (see omc_debug_trace)."""
+        out = np.zeros(max_records * 12)
+        n = C.c_uint32(0)
+        _check(lib().omc_debug_trace(self._h, int(seed), int(h), _dptr(out), max_records,
+                                     C.byref(n)), self._h)
+        return out[: n.value * 12].reshape(n.value, 12)
 
     def counters(self):
         c = Counters()

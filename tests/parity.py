@@ -19,20 +19,26 @@ def batch_sigma(d, d2, B):
     return np.sqrt(np.maximum(d2 / B - d * d, 0.0) / (B - 1))
 
 
-def dose_agreement(dg, d2g, do, d2o, B=10):
-    """Statistical dose comparison inside the oracle's 10 % isodose (Sec. 3.1,
-    Table 1 metrics): fraction of voxels within 2 combined sigma, mean |dD| and
-    signed mean dD relative to Dmax, and the 98th percentile of |dD|/Dmax."""
-    Dmax = do.max()
-    sel = do >= 0.1 * Dmax
-    s = np.sqrt(batch_sigma(dg, d2g, B) ** 2 + batch_sigma(do, d2o, B) ** 2)
+def dose_agreement(dg, d2g, do, d2o, ref, B=10):
+    """Statistical dose comparison inside the 10 % isodose (Sec. 3.1, Table 1
+    metrics): fraction of voxels within 2 combined sigma, mean |dD| and signed
+    mean dD relative to Dmax, and the 98th percentile of |dD|/Dmax.
+
+    The isodose set and Dmax come from ``ref``, a third run independent of both
+    doses compared: selecting on either noisy dose itself biases the difference
+    (the voxels picked are those whose noise happened to be high)."""
+    sg, so = batch_sigma(dg, d2g, B), batch_sigma(do, d2o, B)
+    Dmax = ref.max()
+    sel = ref >= 0.1 * Dmax
+    comb = ref
+    s = np.sqrt(sg**2 + so**2)
     diff = dg[sel] - do[sel]
     within = np.mean(np.abs(diff) <= 2 * s[sel])
     return {"n": int(sel.sum()), "within2s": float(within),
             "mean_abs": float(np.mean(np.abs(diff)) / Dmax),
             "bias": float(np.mean(diff) / Dmax),
             "p98": float(np.percentile(np.abs(diff), 98) / Dmax),
-            "sigma_rel": float(np.mean(s[sel] / do[sel]))}
+            "sigma_rel": float(np.mean(s[sel] / comb[sel]))}
 
 
 def counter_z(cg, co, ng, no):
