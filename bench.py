@@ -49,13 +49,14 @@ def cpu_baseline(ph, src, target_s, threads):
     oracle.lib()
     # calibrate on two sizes so that the fixed set-up cost (tables, grids) is
     # separated from the per-history cost
-    times = []
-    for n in (2000, 20000):
+    sizes, times = (20_000, 200_000), []
+    for n in sizes:
         t = time.perf_counter()
         oracle.run(ph, src, n, seed=7, threads=threads)
         times.append(time.perf_counter() - t)
-    per_hist = max((times[1] - times[0]) / 18000, 1e-9)
-    n_sample = int(max(20000, min(50_000_000, (target_s - times[0]) / per_hist)))
+    per_hist = max((times[1] - times[0]) / (sizes[1] - sizes[0]), 1e-8)
+    setup = max(times[0] - sizes[0] * per_hist, 0.0)
+    n_sample = int(max(sizes[1], min(1_000_000_000, (target_s - setup) / per_hist)))
     t = time.perf_counter()
     oracle.run(ph, src, n_sample, seed=7, threads=threads)
     dt = time.perf_counter() - t
@@ -74,7 +75,20 @@ def main():
     ap.add_argument("--parity-fp64", action="store_true", help="time the FP64 parity build")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (hardware-counter "
+                         "calibration of FETCH_SIZE / WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 2**30) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        y = x.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                          "check": float(y[-1].item())}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(the history-range sharding design is described in DESIGN.md)", file=sys.stderr)

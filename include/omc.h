@@ -96,8 +96,8 @@ typedef struct {
     int csda_mode;           /* 1: no hinge, no multiple scattering, no hard events */
     int block_size;          /* work-items per work-group (256); multiple of 64 */
     int blocks_per_cu;       /* resident work-groups per CU for the transport grid (4) */
-    int chunk_histories;     /* histories per source chunk (0 = automatic) */
-    int queue_factor;        /* secondary queue capacity per source history (8) */
+    int chunk_histories;     /* histories per source chunk (0 = min(n, 2^24)) */
+    int queue_factor;        /* secondary queue capacity per source history (6) */
     int timing;              /* 1: record per-kernel HIP event times */
 } omc_params;
 

@@ -49,6 +49,7 @@ enum Energy : int { EN_INCIDENT = 0, EN_DEPOSITED, EN_ESCAPED, kNumEnergies };
 
 enum PType : int { PT_PHOTON = 0, PT_ELECTRON = 1, PT_POSITRON = 2 };
 
+constexpr uint32_t kResBlockSlots = 128;  // output slots a wave reserves per atomic
 constexpr int kTabNE = 512;
 constexpr int kTabNA = 512;
 
@@ -104,8 +105,9 @@ struct TallyView {
 };
 
 struct StatsView {
-    unsigned long long* counters;  // [kNumCounters]
-    double* energies;              // [kNumEnergies]
+    unsigned long long* counters;  // [n_rows][kNumCounters], summed at the end of a run
+    double* energies;              // [n_rows][kNumEnergies]
+    uint32_t n_rows;
     uint32_t* overflow;            // set to 1 when a push found its queue full
     uint32_t* max_steps;           // longest particle (steps) of the run
 };
@@ -175,6 +177,10 @@ struct Launch {
 int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,
                 double V, double n_total, double* dose, double* dose2, void* stream);
 int launch_queue_reset(uint32_t* ctrl, int which_mask, void* stream);
+// Sum the per-work-group statistics rows into row 0.
+int launch_stats_reduce(unsigned long long* counters, double* energies, uint32_t n_rows,
+                        void* stream);
+constexpr uint32_t kStatsRows = 1024;
 int launch_philox_debug(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
                         uint32_t* out, void* stream);
 

@@ -64,6 +64,31 @@ int launch_queue_reset(uint32_t* ctrl, int mask, void* stream)
     return detail::launch_status();
 }
 
+// Row-wise sum of the statistics buffer into row 0 (one work-group).
+__global__ void stats_reduce_kernel(unsigned long long* counters, double* energies,
+                                    uint32_t n_rows)
+{
+    const int k = threadIdx.x;
+    if (k < kNumCounters) {
+        unsigned long long s = 0;
+        for (uint32_t r = 0; r < n_rows; ++r) s += counters[size_t(r) * kNumCounters + k];
+        counters[k] = s;
+    } else if (k < kNumCounters + kNumEnergies) {
+        const int j = k - kNumCounters;
+        double s = 0.0;
+        for (uint32_t r = 0; r < n_rows; ++r) s += energies[size_t(r) * kNumEnergies + j];
+        energies[j] = s;
+    }
+}
+
+int launch_stats_reduce(unsigned long long* counters, double* energies, uint32_t n_rows,
+                        void* stream)
+{
+    hipLaunchKernelGGL(stats_reduce_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, counters,
+                       energies, n_rows);
+    return detail::launch_status();
+}
+
 __global__ void philox_debug_kernel(uint32_t seed, uint32_t h, uint32_t qlo, uint32_t qhi,
                                     uint32_t n0, uint32_t nblocks, uint32_t* out)
 {

@@ -371,9 +371,13 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     const omc_params& P = c->prm;
     const int B = P.n_batches;
     const uint64_t chunk =
-        P.chunk_histories > 0 ? uint64_t(P.chunk_histories) : std::min<uint64_t>(N, uint64_t(1) << 22);
+        P.chunk_histories > 0 ? uint64_t(P.chunk_histories) : std::min<uint64_t>(N, uint64_t(1) << 24);
     const uint64_t S = std::min<uint64_t>(chunk, N);
-    const uint64_t qcap = std::min<uint64_t>(uint64_t(P.queue_factor) * S + 4096, 0x7fffffffull);
+    // capacity: secondaries per source history, plus the holes left by the
+    // per-wave slot reservations of the two kernels that append to a queue
+    const uint64_t waves = uint64_t(c->cu_count) * P.blocks_per_cu * (P.block_size / 64);
+    const uint64_t qcap = std::min<uint64_t>(
+        uint64_t(P.queue_factor) * S + 2 * waves * omc::kResBlockSlots + 4096, 0x7fffffffull);
     if ((rc = ensure_queues(c, Q, uint32_t(std::max<uint64_t>(qcap, S)), uint32_t(qcap)))) return rc;
 
     // tally grids
@@ -398,8 +402,11 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     tm.s = s;
 
     HIP_TRY(c, hipMemsetAsync(c->d_grid, 0, need * sizeof(double), s));
-    HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, omc::kNumCounters * sizeof(unsigned long long), s));
-    HIP_TRY(c, hipMemsetAsync(c->d_energies, 0, omc::kNumEnergies * sizeof(double), s));
+    HIP_TRY(c, hipMemsetAsync(c->d_counters, 0,
+                              size_t(omc::kStatsRows) * omc::kNumCounters *
+                                  sizeof(unsigned long long), s));
+    HIP_TRY(c, hipMemsetAsync(c->d_energies, 0,
+                              size_t(omc::kStatsRows) * omc::kNumEnergies * sizeof(double), s));
     HIP_TRY(c, hipMemsetAsync(c->d_ctrl, 0, 16 * sizeof(uint32_t), s));
 
     omc::KernelArgs<R> a{};
@@ -427,7 +434,7 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     a.prm = {R(P.Eabs_e), R(P.Eabs_g), R(P.Wcc), R(P.kc), R(P.dmax_s), R(1.0 - P.f_E), R(skin),
              P.kerma_mode, P.csda_mode};
     a.tally = {c->d_grid, c->nvox, N, h0, B};
-    a.stats = {c->d_counters, c->d_energies, c->d_ctrl + 8, c->d_ctrl + 9};
+    a.stats = {c->d_counters, c->d_energies, omc::kStatsRows, c->d_ctrl + 8, c->d_ctrl + 9};
     const omc_source& sr = c->src;
     a.src.cdf = c->d_cdf;
     a.src.edges = T.edges;
@@ -527,6 +534,8 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     tm.end();
     unsigned long long cnts[omc::kNumCounters];
     double en[omc::kNumEnergies];
+    if (omc::launch_stats_reduce(c->d_counters, c->d_energies, omc::kStatsRows, s))
+        return fail(c, OMC_EDEVICE, "statistics reduce launch failed");
     HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost,
                               s));
     HIP_TRY(c, hipMemcpyAsync(cnts, c->d_counters, sizeof cnts, hipMemcpyDeviceToHost, s));
@@ -572,7 +581,7 @@ void omc_default_params(omc_params* p)
     p->block_size = 256;
     p->blocks_per_cu = 4;
     p->chunk_histories = 0;
-    p->queue_factor = 8;
+    p->queue_factor = 6;
     p->timing = 0;
 }
 
@@ -634,9 +643,10 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
     bool ok = hipMalloc(&c->d_rho, c->nvox * sizeof(float)) == hipSuccess &&
               hipMalloc(&c->d_mat, c->nvox) == hipSuccess &&
               hipMalloc(&c->d_ctrl, 64 * sizeof(uint32_t)) == hipSuccess &&
-              hipMalloc(&c->d_counters, omc::kNumCounters * sizeof(unsigned long long)) ==
-                  hipSuccess &&
-              hipMalloc(&c->d_energies, omc::kNumEnergies * sizeof(double)) == hipSuccess &&
+              hipMalloc(&c->d_counters, size_t(omc::kStatsRows) * omc::kNumCounters *
+                                            sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&c->d_energies, size_t(omc::kStatsRows) * omc::kNumEnergies *
+                                            sizeof(double)) == hipSuccess &&
               hipHostMalloc(&c->h_ctrl, 64 * sizeof(uint32_t)) == hipSuccess;
     ok = ok && hipMemcpy(c->d_rho, c->rho.data(), c->nvox * sizeof(float), hipMemcpyHostToDevice) ==
                    hipSuccess;

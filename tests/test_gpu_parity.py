@@ -193,14 +193,15 @@ def test_errors(omc, W):
     with pytest.raises(omc.OmcError) as e:
         eng.set_params(f_E=1.5)
     assert e.value.code == omc.OMC_EINVAL
-    # a queue far too small for the secondaries of 15 MeV electrons
-    # (capacity = factor * chunk + 4096 records; 15 MeV primaries make ~3 deltas each)
-    eng.set_params(chunk_histories=50_000, queue_factor=1)
+    # a queue far too small for the secondaries of 15 MeV electrons: capacity is
+    # factor * chunk + 2 * waves * 128 reserved-slot slack + 4096 records, here
+    # 5e5 + 2.6e5 + 4096, while 5e5 primaries make about 1.5e6 deltas
+    eng.set_params(chunk_histories=500_000, queue_factor=1, blocks_per_cu=1)
     with pytest.raises(omc.OmcError) as e:
-        eng.run(50_000)
+        eng.run(500_000)
     assert e.value.code == omc.OMC_EQUEUE
     # the context stays usable afterwards
-    eng.set_params(chunk_histories=0, queue_factor=8)
+    eng.set_params(chunk_histories=0, queue_factor=8, blocks_per_cu=4)
     d, _ = eng.run(500)
     assert d.sum() > 0
     eng.close()
