@@ -64,28 +64,43 @@ int launch_queue_reset(uint32_t* ctrl, int mask, void* stream)
     return detail::launch_status();
 }
 
-// Row-wise sum of the statistics buffer into row 0 (one work-group).
-__global__ void stats_reduce_kernel(unsigned long long* counters, double* energies,
-                                    uint32_t n_rows)
+// Column sums of the statistics buffer into row 0: one work-group per column,
+// 256 threads striding over the rows, then a tree in LDS.
+__global__ void __launch_bounds__(256) stats_reduce_kernel(unsigned long long* counters,
+                                                          double* energies, uint32_t n_rows)
 {
-    const int k = threadIdx.x;
-    if (k < kNumCounters) {
-        unsigned long long s = 0;
-        for (uint32_t r = 0; r < n_rows; ++r) s += counters[size_t(r) * kNumCounters + k];
-        counters[k] = s;
-    } else if (k < kNumCounters + kNumEnergies) {
-        const int j = k - kNumCounters;
-        double s = 0.0;
-        for (uint32_t r = 0; r < n_rows; ++r) s += energies[size_t(r) * kNumEnergies + j];
-        energies[j] = s;
+    __shared__ unsigned long long su[256];
+    __shared__ double sd[256];
+    const int col = blockIdx.x;
+    const bool is_count = col < kNumCounters;
+    const int j = is_count ? col : col - kNumCounters;
+    unsigned long long u = 0;
+    double v = 0.0;
+    for (uint32_t r = threadIdx.x; r < n_rows; r += blockDim.x) {
+        if (is_count) u += counters[size_t(r) * kNumCounters + j];
+        else v += energies[size_t(r) * kNumEnergies + j];
+    }
+    su[threadIdx.x] = u;
+    sd[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) {
+            su[threadIdx.x] += su[threadIdx.x + s];
+            sd[threadIdx.x] += sd[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (is_count) counters[j] = su[0];
+        else energies[j] = sd[0];
     }
 }
 
 int launch_stats_reduce(unsigned long long* counters, double* energies, uint32_t n_rows,
                         void* stream)
 {
-    hipLaunchKernelGGL(stats_reduce_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, counters,
-                       energies, n_rows);
+    hipLaunchKernelGGL(stats_reduce_kernel, dim3(kNumCounters + kNumEnergies), dim3(256), 0,
+                       (hipStream_t)stream, counters, energies, n_rows);
     return detail::launch_status();
 }
 

@@ -462,6 +462,12 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
 
     const int block = P.block_size;
     const int tgrid = c->cu_count * P.blocks_per_cu;
+    // a generation with few records needs fewer persistent work-groups: about
+    // two records per lane, never fewer than one work-group per CU
+    auto grid_for = [&](uint32_t n_records) {
+        const uint64_t want = (uint64_t(n_records) + 2ull * block - 1) / (2ull * block);
+        return int(std::max<uint64_t>(c->cu_count, std::min<uint64_t>(want, uint64_t(tgrid))));
+    };
     const int nm = int(c->mats.size());
     const size_t lds_ph = omc::photon_lds_bytes<R>(nm);
     const size_t lds_el = omc::electron_lds_bytes<R>(nm);
@@ -493,16 +499,17 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
                 a.qe_out = Q.q[ec];
                 a.qp_out = Q.q[pc ^ 1];
                 tm.begin(1);
-                if (omc::Launch<R>::photon(a, tgrid, block, lds_ph, s))
+                if (omc::Launch<R>::photon(a, grid_for(n_ph), block, lds_ph, s))
                     return fail(c, OMC_EDEVICE, "photon kernel launch failed");
                 tm.end();
             }
-            // electrons created by the photon kernel are in Q.q[ec]
+            // electrons created by the photon kernel are in Q.q[ec]; their count
+            // is known on the host only when no photon kernel ran before
             a.qin = Q.q[ec];
             a.qe_out = Q.q[ec ^ 1];
             a.qp_out = Q.q[pc ^ 1];
             tm.begin(2);
-            if (omc::Launch<R>::electron(a, tgrid, block, lds_el, s))
+            if (omc::Launch<R>::electron(a, n_ph ? tgrid : grid_for(n_el), block, lds_el, s))
                 return fail(c, OMC_EDEVICE, "electron kernel launch failed");
             tm.end();
             if (omc::launch_queue_reset(c->d_ctrl, (1 << pc) | (1 << ec), s))
