@@ -1,15 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of the coupled photon-electron Monte Carlo engine on one MI355X.
 
-A step is one full transport run (source, photon and electron generations,
-FP64 tally fold) of the workload's histories, with phantom, tables and output
-buffers resident in HBM before the timed region. Default workload: 6 MV photons
-(64-bin synthetic spectrum), 10x10 cm^2 field at SSD 100 cm, 128^3 slab of
-0.25 cm voxels (water / bone 1.85 / lung 0.26 / water), 1e7 histories per step.
+A step is one full transport run (source, photon and electron generations in
+the launch shape given, FP64 tally fold) of the workload's histories, with
+phantom, tables and output buffers resident in HBM before the timed region.
+Default workload: 6 MV photons (64-bin synthetic spectrum), 10x10 cm^2 field at
+SSD 100 cm, 128^3 slab of 0.25 cm voxels (water / bone 1.85 / lung 0.26 /
+water), 1e7 histories per step, generations replayed from a captured graph.
+The batched workload (--workload beamlets_c4) steps through 512 beamlets on a
+256 x 256 x 160 CT-like phantom with per-beamlet sparse output left in HBM.
 
 Prints one JSON line: histories/s, time to 1 % sigma at Dmax, the ALU roofline
 of the dominant kernel (algorithmic lane operations per launch over its
-HIP-event launch time) and the CPU oracle timed on a bounded sample.
+HIP-event launch time, from an instrumented pass of the same steps right after
+the timed region: HIP events cannot time kernels inside a graph) and the CPU
+oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -39,6 +44,18 @@ WORKLOADS = {
                  "1e4 histories per step",
     "halfslab_e15": "15 MeV electrons, 10x10 cm2 at SSD 100 cm, 256^3 half-slab of 0.2 cm voxels, "
                     "1e8 histories per step",
+    "beamlets_c4": "512 beamlets 0.5x0.5 cm2 of 6 MV (8 gantry angles x 8x8), 1e5-1e6 histories "
+                   "each (2.84e8 in all), 256x256x160 CT-like phantom of 0.2 cm voxels (12 "
+                   "seeded ellipsoids, 0.2-1.9 g/cm3), per-beamlet sparse FP32 dose in HBM",
+}
+
+# launch shape per workload: graph generations per source chunk, histories per
+# chunk (0 = 2^24), work-groups per CU (what omc_autotune picks on MI355X; the
+# --autotune flag re-runs it)
+SHAPES = {
+    "slab_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 8},
+    "water_e15": {"graph_depth": 8, "chunk_histories": 0, "blocks_per_cu": 4},
+    "halfslab_e15": {"graph_depth": 6, "chunk_histories": 0, "blocks_per_cu": 8},
 }
 
 
@@ -65,6 +82,40 @@ def cpu_baseline(ph, src, target_s, threads):
                       f"{dt:.1f} s"}
 
 
+def roofline_of(kt, units):
+    """ALU roofline of the dominant transport kernel from per-kernel HIP-event
+    times kt and the event counters units of the same steps."""
+    dom = max(("photon", "electron"), key=lambda k: kt[k][0])
+    ops = sum(units.get(k, 0) * w for k, w in OPS[dom].items())
+    t_dom = kt[dom][0] / 1e3
+    launches = max(kt[dom][1], 1)
+    achieved = ops / t_dom / 1e12
+    return {"bound": "alu", "kernel": f"{dom}_kernel", "achieved": achieved,
+            "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "frac": achieved / PEAK_ALU_TOPS,
+            "traffic": None, "launches": launches, "avg_launch_ms": kt[dom][0] / launches,
+            "ops_per_launch": ops / launches}
+
+
+def cpu_baseline_beamlets(ph, job, target_s, threads):
+    """The oracle on a bounded sample of the batched workload: whole beamlets,
+    each at a reduced history count, every 16th beamlet (all gantry angles)."""
+    from oracle import oracle
+    oracle.lib()
+    sample = job[::16]
+    t = time.perf_counter()
+    per = 2000
+    oracle.run_beamlets(ph, [(s, per, h) for s, _, h in sample], seed=7, threads=threads)
+    dt = time.perf_counter() - t
+    per = int(max(per, min(10**6, per * target_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    oracle.run_beamlets(ph, [(s, per, h) for s, _, h in sample], seed=7, threads=threads)
+    dt = time.perf_counter() - t
+    n = per * len(sample)
+    return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} of the 512 beamlets, {per} histories each "
+                      f"({n} in all, FP64 C oracle, OpenMP), {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +124,14 @@ def main():
     ap.add_argument("--workload", default="slab_6mv", choices=sorted(WORKLOADS))
     ap.add_argument("--histories", type=int, default=0, help="override histories per step")
     ap.add_argument("--parity-fp64", action="store_true", help="time the FP64 parity build")
+    ap.add_argument("--graph-depth", type=int, default=-1, help="override the launch shape")
+    ap.add_argument("--chunk", type=int, default=-1)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shape with omc_autotune before the warm-up")
+    ap.add_argument("--no-timing-pass", action="store_true",
+                    help="skip the instrumented pass (no roofline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
@@ -101,59 +160,65 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    ph, src, n = W.config(args.workload)
+    beamlets = args.workload == "beamlets_c4"
+    if beamlets:
+        ph = W.ellipsoid_phantom()
+        job = W.beamlet_job(ph)
+        src, n = job[0][0], sum(b[1] for b in job)
+        shape = {"graph_depth": W.BEAMLET_GRAPH_DEPTH, "chunk_histories": W.BEAMLET_CHUNK,
+                 "blocks_per_cu": W.BEAMLET_BLOCKS_PER_CU}
+    else:
+        ph, src, n = W.config(args.workload)
+        shape = dict(SHAPES[args.workload])
     if args.histories:
         n = args.histories
+    for k, v in (("graph_depth", args.graph_depth), ("chunk_histories", args.chunk)):
+        if v >= 0:
+            shape[k] = v
+    if args.blocks_per_cu:
+        shape["blocks_per_cu"] = args.blocks_per_cu
+    if args.block_size:
+        shape["block_size"] = args.block_size
     eng = omc.Engine(ph)
     eng.set_source(src)
-    eng.set_params(timing=1, parity_fp64=int(args.parity_fp64))
+    eng.set_params(parity_fp64=int(args.parity_fp64), **shape)
+    if args.autotune:
+        t = time.perf_counter()
+        shape = eng.autotune(min(n, 1 << 24), seed=99)
+        print(f"autotune {time.perf_counter() - t:.1f} s: "
+              + " ".join(f"{k}={shape[k]}" for k in ("block_size", "blocks_per_cu",
+                                                     "chunk_histories", "graph_depth",
+                                                     "queue_factor")), file=sys.stderr)
     nvox = int(np.prod(ph["shape"]))
-    dose = torch.zeros(nvox, dtype=torch.float64, device="cuda")
-    dose2 = torch.zeros_like(dose)
     stream = torch.cuda.current_stream()
+    if beamlets:
+        nnz = [0]
 
-    h = 0
-    for _ in range(args.warmup):
-        eng.run_device(n, 1, h, dose, dose2, stream)
-        h = (h + n) % (2**32 - n)
-    kt = {"photon": [0.0, 0], "electron": [0.0, 0], "source": [0.0, 0], "fold": [0.0, 0]}
-    units = {}
+        def step(seed):
+            sp = eng.run_beamlets(job, seed=seed, on_device=True, stream=stream)
+            nnz[0] = sp.nnz
+            sp.free()
+    else:
+        dose = torch.zeros(nvox, dtype=torch.float64, device="cuda")
+        dose2 = torch.zeros_like(dose)
+        hh = [0]
+
+        def step(seed):
+            eng.run_device(n, seed, hh[0], dose, dose2, stream)
+            hh[0] = (hh[0] + n) % (2**32 - n)
+
+    for w in range(args.warmup):
+        step(1 + w)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        eng.run_device(n, 1, h, dose, dose2, stream)
-        h = (h + n) % (2**32 - n)
-        tm = eng.timing()
-        for k in kt:
-            kt[k][0] += tm["total_ms"][k]
-            kt[k][1] += tm["launches"][k]
-        c = eng.counters()
-        for k, v in c.items():
-            units[k] = units.get(k, 0) + v
+    for k in range(args.steps):
+        step(100 + k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
-
-    # time to 1 % sigma at Dmax from the last step's batch estimate
-    d = dose.cpu().numpy()
-    d2 = dose2.cpu().numpy()
-    B = eng.params.n_batches
-    sig = np.sqrt(np.maximum(d2 / B - d * d, 0) / (B - 1))
-    hot = d >= 0.9 * d.max()
-    sbar = float(np.mean(sig[hot] / d[hot]))
-    t1pct = (ms_per_step / 1e3) * (sbar / 0.01) ** 2
-
-    dom = max(("photon", "electron"), key=lambda k: kt[k][0])
-    ops = sum(units.get(k, 0) * w for k, w in OPS[dom].items())
-    t_dom = kt[dom][0] / 1e3
-    launches = max(kt[dom][1], 1)
-    achieved = ops / t_dom / 1e12
-    roofline = {"bound": "alu", "kernel": f"{dom}_kernel", "achieved": achieved,
-                "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "frac": achieved / PEAK_ALU_TOPS,
-                "traffic": None, "launches": launches,
-                "avg_launch_ms": kt[dom][0] / launches,
-                "ops_per_launch": ops / launches}
+    c = eng.counters()
+    params = eng.params.as_dict()
 
     out = {"metric": "histories/s", "value": value, "unit": "histories/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -161,16 +226,51 @@ def main():
            "dtype": "f64" if args.parity_fp64 else "f32", "data": "synthetic",
            "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                       "histories_per_step": n, "transport": "fp64" if args.parity_fp64 else "fp32",
-                      "tally": "fp64", "batches": B},
-           "s_to_1pct_sigma_at_Dmax": t1pct, "sigma_rel_at_Dmax": sbar,
-           "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
-           "events_per_history": {k: units[k] / (n * args.steps) for k in
-                                  ("ph_flights", "ph_compton", "el_steps", "el_moller")},
-           "max_steps_per_particle": c["max_steps"], "watchdog": units.get("watchdog", 0),
-           "roofline": roofline}
-    if not args.no_cpu_baseline:
+                      "tally": "fp64",
+                      "launch": {k: params[k] for k in ("block_size", "blocks_per_cu",
+                                                        "chunk_histories", "graph_depth",
+                                                        "queue_factor")}}}
+    if not beamlets:
+        # time to 1 % sigma at Dmax from the last step's batch estimate
+        d = dose.cpu().numpy()
+        d2 = dose2.cpu().numpy()
+        B = eng.params.n_batches
+        sig = np.sqrt(np.maximum(d2 / B - d * d, 0) / (B - 1))
+        hot = d >= 0.9 * d.max()
+        sbar = float(np.mean(sig[hot] / d[hot]))
+        out["config"]["batches"] = B
+        out["s_to_1pct_sigma_at_Dmax"] = (ms_per_step / 1e3) * (sbar / 0.01) ** 2
+        out["sigma_rel_at_Dmax"] = sbar
+    else:
+        out["sparse_nnz"] = nnz[0]
+
+    if not args.no_timing_pass:
+        # the same steps again with one HIP event pair per launch
+        eng.set_params(timing=1)
+        kt = {"photon": [0.0, 0], "electron": [0.0, 0], "source": [0.0, 0], "fold": [0.0, 0]}
+        units = {}
+        for k in range(args.steps):
+            step(100 + k)
+            tm = eng.timing()
+            for kk in kt:
+                kt[kk][0] += tm["total_ms"][kk]
+                kt[kk][1] += tm["launches"][kk]
+            for kk, v in eng.counters().items():
+                units[kk] = units.get(kk, 0) + v
+        eng.set_params(timing=0)
+        out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in kt.items()}
+        out["launches_per_step"] = {k: v[1] / args.steps for k, v in kt.items()}
+        out["events_per_history"] = {k: units[k] / (n * args.steps) for k in
+                                     ("ph_flights", "ph_compton", "el_steps", "el_moller")}
+        out["roofline"] = roofline_of(kt, units)
+    out["max_steps_per_particle"] = c["max_steps"]
+    out["watchdog"] = c["watchdog"]
+    if not args.no_cpu_baseline and not beamlets:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(ph, src, args.cpu_seconds, threads)
+    elif not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_beamlets(ph, job, args.cpu_seconds,
+                                                    min(16, os.cpu_count() or 1))
     eng.close()
     print(json.dumps(out), flush=True)
 

@@ -99,6 +99,18 @@ typedef struct {
     int chunk_histories;     /* histories per source chunk (0 = min(n, 2^24)) */
     int queue_factor;        /* secondary queue capacity per source history (6) */
     int timing;              /* 1: record per-kernel HIP event times */
+    int graph_depth;         /* 0: each photon+electron generation is launched from the host,
+                                which reads the queue counts back after it; K in 1..64: the
+                                launches of a run are captured once in a HIP graph, K
+                                generations per source chunk, and replayed by later runs of
+                                the same shape; particles still queued after a chunk's K
+                                generations carry over into the next chunk's, and those left
+                                after the last chunk are drained from the host (0) */
+    int beamlet_group;       /* beamlets tallied together by omc_run_beamlets; 0 = as many as
+                                half of the free device memory holds (0) */
+    double sparse_threshold; /* omc_run_beamlets keeps a voxel when its dose exceeds this
+                                fraction of the beamlet's largest voxel dose; 0 = every voxel
+                                with a positive FP32 dose (0) */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */
@@ -114,9 +126,11 @@ typedef struct {
 } omc_counters;
 
 /* Per-kernel timing of the last run (params.timing == 1), HIP events on the
- * run's stream. */
+ * run's stream. HIP events cannot time the kernels of a graph, so with
+ * graph_depth > 0 a timed run launches the same fixed-depth sequence without
+ * capturing it. */
 typedef struct {
-    uint32_t launches[4];    /* 0 source, 1 photon, 2 electron, 3 fold */
+    uint32_t launches[4];    /* 0 source, 1 photon, 2 electron, 3 fold or compaction */
     double total_ms[4];
     double run_ms;           /* whole run, first launch to last */
 } omc_timing;
@@ -149,6 +163,58 @@ int omc_run(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* dose,
  * complete on that stream. */
 int omc_run_device(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* d_dose,
                    double* d_dose2, void* hip_stream);
+
+/* One beamlet of a batched run: a source with its own history count and
+ * history ids. (The paper transports one beam per run and tunes only the
+ * number of work-items per launch, Sec. 2.2.2; batching many small beams into
+ * one run keeps the device full where one beamlet alone cannot.) */
+typedef struct {
+    omc_source src;          /* geometry and spectrum; arrays read during the call */
+    uint64_t n_histories;    /* >= 1 */
+    uint32_t h0;             /* histories h0 .. h0+n-1, streams keyed by (seed, h); h0 + n <= 2^32 */
+} omc_beamlet;
+
+/* Per-beamlet dose in compressed sparse rows. Allocated by omc_run_beamlets,
+ * released with omc_free_sparse. */
+typedef struct {
+    int n_beamlets;
+    int on_device;           /* 1: voxel and dose are device memory of the context's device */
+    uint64_t nnz;
+    uint64_t* row_ptr;       /* host memory, n_beamlets + 1: beamlet b owns [row_ptr[b], row_ptr[b+1]) */
+    uint32_t* voxel;         /* nnz linear voxel indices (x fastest), increasing within a row */
+    float* dose;             /* nnz doses, MeV/g per history of that beamlet */
+} omc_sparse_out;
+
+/* Transport n_beamlets beams in one run per group of params.beamlet_group
+ * beamlets: their histories are interleaved in the same source chunks and
+ * particle generations (one launch sequence, a captured graph when
+ * graph_depth > 0), each beamlet tallied in an FP64 grid of its own, and every
+ * grid compacted on the device into the CSR rows of *out (FP32 dose, voxels
+ * kept per sparse_threshold). The dose of a beamlet equals the dose omc_run
+ * gives for its source, history count and h0 with the same seed (same streams,
+ * same counters; summation order aside). All beamlets must have the same
+ * particle type. on_device: 1 leaves voxel and dose in device memory (launched
+ * on hip_stream, NULL = default stream), 0 copies them to host memory.
+ * Counters and timing of the call are those of omc_get_counters/omc_get_timing.
+ * Errors: OMC_EINVAL for a NULL or invalid beamlet (rules of omc_set_source,
+ * n_histories >= 1, 1 <= n_beamlets <= 65535), OMC_EQUEUE, OMC_ENOMEM,
+ * OMC_ENUMERIC as omc_run; *out is zeroed first and left empty on error. */
+int omc_run_beamlets(omc_ctx* ctx, const omc_beamlet* beamlets, int n_beamlets, uint32_t seed,
+                     int on_device, void* hip_stream, omc_sparse_out* out);
+
+/* Release what omc_run_beamlets allocated in *out and zero it. NULL is ignored. */
+void omc_free_sparse(omc_sparse_out* out);
+
+/* Launch-shape autotuner (the paper sets its number of work-items M by hand,
+ * Sec. 2.2.2). Times runs of n_probe histories of the current source with the
+ * current physics parameters over work-group size, work-groups per CU, source
+ * chunk size and graph depth, keeps the fastest, sizes queue_factor from the
+ * queue high-water marks it saw, and applies the result to ctx (as
+ * omc_set_params would). *best receives it when best != NULL. Each candidate
+ * runs three times (the first builds its graph). Errors: OMC_ESTATE without a
+ * source, OMC_EINVAL for n_probe == 0 or > 2^31, run errors if no candidate
+ * completes. */
+int omc_autotune(omc_ctx* ctx, uint64_t n_probe, uint32_t seed, omc_params* best);
 
 int omc_get_counters(const omc_ctx* ctx, omc_counters* out);
 int omc_get_timing(const omc_ctx* ctx, omc_timing* out);

@@ -258,6 +258,19 @@ def run(phantom, source, n, seed=1, h0=0, params=None, threads=None):
     return dose.reshape(shape), dose2.reshape(shape), cnt.as_dict()
 
 
+def run_beamlets(phantom, beamlets, seed=1, params=None, threads=None):
+    """Batched beamlets as the method defines them: beamlet (source, n, h0) is
+    an independent run of histories h0 .. h0+n-1 of its own source with
+    streams keyed by (seed, h). Returns the per-beamlet doses (MeV/g per
+    history of that beamlet) and the counters summed over beamlets."""
+    doses, total = [], None
+    for src, n, h0 in beamlets:
+        d, _, c = run(phantom, src, n, seed=seed, h0=h0, params=params, threads=threads)
+        doses.append(d)
+        total = dict(c) if total is None else {k: total[k] + c[k] for k in total}
+    return doses, total
+
+
 def trace(phantom, source, h, seed=1, params=None, cap=1 << 16):
     """Electron step records of history h alone (see orc_trace)."""
     pr = _ProblemHolder(phantom, source, params)

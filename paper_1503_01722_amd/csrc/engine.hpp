@@ -9,8 +9,12 @@
 //   queues      four structure-of-arrays particle queues (photon cur/next,
 //               electron cur/next), each {x,y,z,u,v,w,E} R, voxel u32 packed
 //               (ix | iy<<10 | iz<<20), history u32, particle id 2 x u32,
-//               type u8; a control block of {count, head} per queue
-//   tally       B batch grids f64[B][nvox] (the one FP64 step on the GPU)
+//               tag u32 (type | tally cell << 8); a control block of
+//               {count, head} per queue
+//   tally       one f64[nvox] grid per tally cell (the one FP64 step on the
+//               GPU): a cell is a batch of a plain run or a beamlet of a
+//               batched-beamlet run
+//   sources     BeamSrc[n_beams], history prefix u64[n_beams + 1], spectra
 //   counters    u64[kNumCounters] and f64 energies[kNumEnergies]
 // R is float for production transport and double for the parity build.
 #pragma once
@@ -60,7 +64,7 @@ struct QueueView {
     uint32_t* hist;
     uint32_t* qlo;
     uint32_t* qhi;
-    uint8_t* type;
+    uint32_t* tag;    // type | cell << 8; kHoleTag for a reserved, unfilled slot
     uint32_t* count;  // number of records written (atomic append)
     uint32_t* head;   // next record to hand out (atomic take)
     uint32_t cap;
@@ -97,11 +101,16 @@ struct ParamView {
 };
 
 struct TallyView {
-    double* grid;        // [B][nvox]
+    double* grid;        // [cells][nvox]
     size_t nvox;
+};
+
+// Values that change from run to run, read by the kernels from device memory
+// so that a captured launch sequence can be replayed for another run.
+struct RunDesc {
+    uint32_t seed;
+    uint32_t n_batches;  // cells of a plain run
     uint64_t n_total;    // histories of the run
-    uint32_t h0;
-    int B;
 };
 
 struct StatsView {
@@ -110,19 +119,32 @@ struct StatsView {
     uint32_t n_rows;
     uint32_t* overflow;            // set to 1 when a push found its queue full
     uint32_t* max_steps;           // longest particle (steps) of the run
+    uint32_t* hwm;                 // [2] queue high-water marks in slots: electrons, photons
+};
+
+// One beam of a run: a plain run has one, a batched-beamlet run one per
+// beamlet. Spectra of all beams are concatenated in SourceView::cdf / edges.
+template <typename R>
+struct BeamSrc {
+    R mono_E;
+    R ssd, z_field, fx, fy, cx, cy, sx, sy;
+    R cg, sg, iso_x, iso_z;  // cos/sin of the gantry angle (host FP64)
+    int n_bins;              // 0: mono-energetic
+    int cdf_off, edge_off;   // first entry of this beam's cdf / edges
+    int point;               // 1 point source
+    int rotate;              // gantry != 0
+    uint32_t h0;             // history id of the beam's first history
 };
 
 template <typename R>
 struct SourceView {
-    const double* cdf;   // n_bins, FP64 running sum normalised by its last entry
-    const R* edges;      // n_bins + 1
-    int n_bins;
-    int particle;        // 0 photon, 1 electron
-    int point;           // 1 point source
-    R mono_E;
-    R ssd, z_field, fx, fy, cx, cy, sx, sy;
-    int rotate;          // gantry != 0
-    R cg, sg, iso_x, iso_z;  // cos/sin of the gantry angle (host FP64)
+    const BeamSrc<R>* beams;
+    const uint64_t* first;  // [n_beams + 1] prefix sums of the beams' history counts
+    const double* cdf;      // per beam n_bins, FP64 running sum normalised by its last entry
+    const R* edges;         // per beam n_bins + 1
+    int n_beams;
+    int particle;           // 0 photon, 1 electron (all beams of a run)
+    int cell_mode;          // 0: cell = batch of the history; 1: cell = beam index
 };
 
 // Step trace of one history (debugging aid): 12 doubles per electron step.
@@ -147,10 +169,11 @@ struct KernelArgs {
     StatsView stats;
     SourceView<R> src;
     TraceView trace;
-    uint32_t seed;
-    uint32_t src_begin;   // first history of this source chunk (relative to h0)
+    const RunDesc* run;
+    uint64_t src_begin;   // first job history of this source chunk
     uint32_t src_count;
     int chunk;            // records a wave takes from the input queue at once
+    int min_grid;         // fewest work-groups a transport generation keeps
 };
 
 // LDS bytes a transport work-group stages (tables of all materials).
@@ -169,6 +192,7 @@ inline size_t electron_lds_bytes(int n_mats)
 // Host-side launchers (one instantiation per precision).
 template <typename R>
 struct Launch {
+    static int prepare(size_t lds_ph, size_t lds_el);
     static int source(const KernelArgs<R>& a, int grid, int block, void* stream);
     static int photon(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream);
     static int electron(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream);
@@ -177,10 +201,34 @@ struct Launch {
 int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,
                 double V, double n_total, double* dose, double* dose2, void* stream);
 int launch_queue_reset(uint32_t* ctrl, int which_mask, void* stream);
+// count of queue `which` += add (appends a source chunk written past the
+// records already waiting in that queue)
+int launch_queue_commit(uint32_t* ctrl, int which, uint32_t add, void* stream);
+// zero n 64-bit words (a kernel, so that it can sit inside a captured graph)
+int launch_zero(void* p, size_t n_words, void* stream);
 // Sum the per-work-group statistics rows into row 0.
 int launch_stats_reduce(unsigned long long* counters, double* energies, uint32_t n_rows,
                         void* stream);
 constexpr uint32_t kStatsRows = 1024;
+
+// Batched-beamlet output: the dense FP64 grid of each beam in a group is
+// compacted to CSR rows of (voxel u32, dose f32) in three passes over tiles of
+// kCompactTile voxels: per-tile counts, an exclusive scan of the counts (the
+// output offsets, in beam-major then voxel order), and the ordered write.
+// scale[b] = 1 / (V * n_b) turns a cell energy into MeV/g per history of beam
+// b once divided by the voxel density; a voxel is kept when its dose is
+// non-zero and above thr[b].
+constexpr int kCompactTile = 2048;
+int launch_beam_max(const double* grid, const float* rho, size_t nvox, int n_beams,
+                    const double* scale, float* dmax, void* stream);
+int launch_compact_count(const double* grid, const float* rho, size_t nvox, int n_beams,
+                         const double* scale, const float* thr, uint32_t* tile_cnt, void* stream);
+// exclusive scan of n counts into out[0..n] (out[n] = total); tmp holds
+// (n + 1023) / 1024 + 1 words
+int launch_scan(const uint32_t* in, uint64_t* out, size_t n, uint64_t* tmp, void* stream);
+int launch_compact_write(const double* grid, const float* rho, size_t nvox, int n_beams,
+                         const double* scale, const float* thr, const uint64_t* tile_off,
+                         uint64_t nnz, uint32_t* voxel, float* dose, void* stream);
 int launch_philox_debug(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
                         uint32_t* out, void* stream);
 

@@ -20,13 +20,25 @@ int Launch<R>::source(const KernelArgs<R>& a, int grid, int block, void* stream)
     return detail::launch_status();
 }
 
+// Allow more than 64 KB of dynamic LDS where the tables need it (done before
+// any launch, outside stream capture).
+template <typename R>
+int Launch<R>::prepare(size_t lds_ph, size_t lds_el)
+{
+    if (lds_ph > 65536 &&
+        hipFuncSetAttribute((const void*)photon_kernel<R>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_ph)) != hipSuccess)
+        return -1;
+    if (lds_el > 65536 &&
+        hipFuncSetAttribute((const void*)electron_kernel<R>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_el)) != hipSuccess)
+        return -1;
+    return 0;
+}
+
 template <typename R>
 int Launch<R>::photon(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream)
 {
-    if (lds > 65536 &&
-        hipFuncSetAttribute((const void*)photon_kernel<R>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
-        return -1;
     hipLaunchKernelGGL(photon_kernel<R>, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
     return detail::launch_status();
 }
@@ -34,10 +46,6 @@ int Launch<R>::photon(const KernelArgs<R>& a, int grid, int block, size_t lds, v
 template <typename R>
 int Launch<R>::electron(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream)
 {
-    if (lds > 65536 &&
-        hipFuncSetAttribute((const void*)electron_kernel<R>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
-        return -1;
     hipLaunchKernelGGL(electron_kernel<R>, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
     return detail::launch_status();
 }

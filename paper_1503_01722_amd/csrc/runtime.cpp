@@ -1,20 +1,29 @@
 // runtime.cpp -- host runtime and C ABI (include/omc.h) of the gfx950 engine.
 //
-// One context per phantom. A run (Table 1 of the paper, re-shaped):
-//   for each chunk of source histories:
-//     source kernel -> photon or electron queue
-//     repeat: photon kernel (photon queue -> electrons, annihilation photons)
-//             electron kernel (electron queue -> deltas, bremsstrahlung and
-//             annihilation photons); swap queues; read the queue counts
-//     until both queues are empty
-//   fold the FP64 batch grids into dose and dose^2.
+// One context per phantom. A run transports a job: a list of beams (one for
+// omc_run, one per beamlet for omc_run_beamlets) whose histories are numbered
+// 0 .. N-1 across the beams and tallied in cells (batches, or beamlets):
+//   for each chunk of job histories:
+//     source kernel -> photon or electron queue (after what is waiting there)
+//     generations: photon kernel (photon queue -> electrons, annihilation
+//                  photons, the photon itself until it is absorbed or leaves)
+//                  electron kernel (electron queue -> deltas, bremsstrahlung
+//                  and annihilation photons); swap queues
+//   then fold the batch cells into dose and dose^2, or compact the beamlet
+//   cells into sparse rows.
 // The paper picks the largest of {photon stack, electron stack, source} per
 // iteration and launches M same-type work-items; here each generation drains a
-// whole queue with a persistent grid that keeps every lane busy.
+// whole queue with a persistent grid that keeps every lane busy. Generations
+// are either driven from the host (queue counts read back after each, until
+// both queues are empty) or captured once as a HIP graph with a fixed number
+// of generations per chunk: the kernels size themselves from the counts on the
+// device, particles left after a chunk's generations join the next chunk's,
+// and the host drains what the last chunk leaves.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -70,9 +79,13 @@ struct omc_ctx {
     int cu_count = 0;
     float* d_rho = nullptr;
     uint8_t* d_mat = nullptr;
-    double* d_cdf = nullptr;
     double* d_grid = nullptr;
-    size_t grid_batches = 0;
+    size_t grid_cells = 0;      // tally cells d_grid holds (nvox doubles each)
+    char* d_src = nullptr;      // beams, history prefix, spectra of the current job
+    size_t src_cap = 0;
+    std::vector<char> src_stage;  // host copy of d_src, alive until the run's end
+    omc::RunDesc* d_run = nullptr;
+    omc::RunDesc* h_run = nullptr;  // pinned
     double* d_dose = nullptr;   // fold target of omc_run
     double* d_dose2 = nullptr;
     uint32_t* d_ctrl = nullptr;  // [4][count, head], overflow at [8]
@@ -90,6 +103,17 @@ struct omc_ctx {
     DeviceTables<double> t64;
     DeviceQueues<float> q32;
     DeviceQueues<double> q64;
+
+    // captured launch sequence of the last graph-mode job
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::vector<unsigned char> graph_key;
+    int graph_pc = 0, graph_ec = 2;  // current queues after the graph
+    uint32_t graph_iters = 0;
+
+    // beamlet compaction scratch
+    char* d_cscratch = nullptr;
+    size_t cscratch_cap = 0;
 
     omc_counters last{};
     omc_timing timing{};
@@ -251,8 +275,12 @@ int ensure_queues(omc_ctx* c, DeviceQueues<R>& Q, uint32_t cap_ph, uint32_t cap_
 {
     if (Q.mem && Q.cap_ph >= cap_ph && Q.cap_el >= cap_el) return OMC_OK;
     free_queues(Q);
-    const size_t per = 7 * sizeof(R) + 4 * sizeof(uint32_t) + 1;
-    const size_t bytes = (size_t(cap_ph) * 2 + size_t(cap_el) * 2) * per + 64 * 16;
+    // capacities in multiples of 64 records keep every array 256-byte aligned
+    // with no padding between arrays, so the layout below is exactly `bytes`
+    cap_ph = uint32_t(std::min<uint64_t>((uint64_t(cap_ph) + 63) & ~uint64_t(63), 0x7fffffc0u));
+    cap_el = uint32_t(std::min<uint64_t>((uint64_t(cap_el) + 63) & ~uint64_t(63), 0x7fffffc0u));
+    const size_t per = 7 * sizeof(R) + 5 * sizeof(uint32_t);
+    const size_t bytes = (size_t(cap_ph) * 2 + size_t(cap_el) * 2) * per;
     if (hipMalloc(&Q.mem, bytes) != hipSuccess) {
         Q.mem = nullptr;
         return fail(c, OMC_ENOMEM, "hipMalloc failed for the particle queues");
@@ -280,10 +308,14 @@ int ensure_queues(omc_ctx* c, DeviceQueues<R>& Q, uint32_t cap_ph, uint32_t cap_
         q.hist = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
         q.qlo = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
         q.qhi = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
-        q.type = reinterpret_cast<uint8_t*>(take(cap));
+        q.tag = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
         q.cap = cap;
         q.count = c->d_ctrl + 2 * k;
         q.head = c->d_ctrl + 2 * k + 1;
+    }
+    if (size_t(p - static_cast<char*>(Q.mem)) != bytes) {
+        free_queues(Q);
+        return fail(c, OMC_EUNSUP, "internal error: queue layout does not match its allocation");
     }
     return OMC_OK;
 }
@@ -298,50 +330,83 @@ void batch_sizes(uint64_t N, int B, std::vector<double>& nb)
     }
 }
 
+// HIP events around eager launches (read and destroyed at the end of a run).
 struct EventTimer {
     bool on = false;
     hipStream_t s = nullptr;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
-    hipEvent_t first = nullptr, last = nullptr;
     void begin(int kind)
     {
         if (!on) return;
-        hipEvent_t a, b;
+        hipEvent_t a = nullptr, b = nullptr;
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
         (void)hipEventRecord(a, s);
         ev.push_back({kind, {a, b}});
-        if (!first) first = a;
     }
     void end()
     {
         if (!on) return;
         (void)hipEventRecord(ev.back().second.second, s);
-        last = ev.back().second.second;
+    }
+};
+
+void collect_events(std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>& ev,
+                    omc_timing& t)
+{
+    for (auto& e : ev) {
+        float ms = 0;
+        (void)hipEventSynchronize(e.second.second);
+        (void)hipEventElapsedTime(&ms, e.second.first, e.second.second);
+        t.launches[e.first] += 1;
+        t.total_ms[e.first] += ms;
+    }
+    (void)hipGetLastError();  // a failed event query must not look like a failed launch later
+}
+
+void destroy_events(std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>& ev)
+{
+    for (auto& e : ev) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    ev.clear();
+}
+
+// whole-run wall time on the device: events recorded before the first and
+// after the last launch of a run
+struct RunClock {
+    hipEvent_t a = nullptr, b = nullptr;
+    void start(bool on, hipStream_t s)
+    {
+        if (!on) return;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, s);
+    }
+    void stop(hipStream_t s)
+    {
+        if (a) (void)hipEventRecord(b, s);
     }
     void collect(omc_timing& t)
     {
-        t = omc_timing{};
-        if (!on) return;
-        for (auto& e : ev) {
-            float ms = 0;
-            (void)hipEventSynchronize(e.second.second);
-            (void)hipEventElapsedTime(&ms, e.second.first, e.second.second);
-            t.launches[e.first] += 1;
-            t.total_ms[e.first] += ms;
-        }
-        if (first && last) {
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, first, last);
-            t.run_ms = ms;
-        }
-        for (auto& e : ev) {
-            (void)hipEventDestroy(e.second.first);
-            (void)hipEventDestroy(e.second.second);
-        }
-        ev.clear();
+        if (!a) return;
+        float ms = 0;
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
+        t.run_ms = ms;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        a = b = nullptr;
     }
 };
+
+void drop_graph(omc_ctx* c)
+{
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_key.clear();
+}
 
 int check_ctx(const omc_ctx* c) { return c ? OMC_OK : OMC_EINVAL; }
 
@@ -360,19 +425,193 @@ uint64_t omc_counters::*const kCounterField[omc::kNumCounters] = {
     &omc_counters::el_hinge_trunc, &omc_counters::pos_annihil, &omc_counters::push_ph,
     &omc_counters::push_el,     &omc_counters::src_miss,      &omc_counters::watchdog};
 
+// ------------------------------------------------------------------- sources
+// Checks a source as omc_set_source documents and returns its spectrum as bin
+// edges and the normalised FP64 running sum of the weights.
+int check_source(const omc_source* s, std::vector<double>& edges, std::vector<double>& cdf,
+                 std::string& why)
+{
+    edges.clear();
+    cdf.clear();
+    if (!s) {
+        why = "NULL source";
+        return OMC_EINVAL;
+    }
+    if (s->particle != 0 && s->particle != 1) {
+        why = "particle must be 0 or 1";
+        return OMC_EINVAL;
+    }
+    if (s->geometry != 0 && s->geometry != 1) {
+        why = "geometry must be 0 or 1";
+        return OMC_EINVAL;
+    }
+    if (!(s->fx > 0) || !(s->fy > 0) || !std::isfinite(s->fx) || !std::isfinite(s->fy)) {
+        why = "field size must be > 0";
+        return OMC_EINVAL;
+    }
+    if (s->geometry == 1 && !finite_pos(s->ssd)) {
+        why = "ssd must be > 0";
+        return OMC_EINVAL;
+    }
+    const double chk[] = {s->z_field, s->cx, s->cy, s->sx, s->sy, s->gantry_deg, s->iso_x, s->iso_z};
+    for (double v : chk)
+        if (!std::isfinite(v)) {
+            why = "non-finite source geometry";
+            return OMC_EINVAL;
+        }
+    if (s->n_bins < 0 || s->n_bins > 4096) {
+        why = "n_bins out of range";
+        return OMC_EINVAL;
+    }
+    if (s->n_bins == 0) {
+        if (!(s->mono_E > 0) || !(s->mono_E < omc::kEHi)) {
+            why = "mono_E must be in (0, 20) MeV";
+            return OMC_EINVAL;
+        }
+        return OMC_OK;
+    }
+    if (!s->edges || !s->weights) {
+        why = "spectrum arrays are NULL";
+        return OMC_EINVAL;
+    }
+    edges.assign(s->edges, s->edges + s->n_bins + 1);
+    for (int b = 0; b <= s->n_bins; ++b)
+        if (!(edges[b] > 0) || !(edges[b] < omc::kEHi) || (b && !(edges[b] > edges[b - 1]))) {
+            why = "spectrum edges must increase within (0, 20) MeV";
+            return OMC_EINVAL;
+        }
+    double acc = 0.0;
+    for (int b = 0; b < s->n_bins; ++b) {
+        const double w = s->weights[b];
+        if (!(w >= 0) || !std::isfinite(w)) {
+            why = "spectrum weights must be finite and >= 0";
+            return OMC_EINVAL;
+        }
+        acc += w;
+        cdf.push_back(acc);
+    }
+    if (!(acc > 0)) {
+        why = "empty spectrum";
+        return OMC_EINVAL;
+    }
+    for (double& v : cdf) v = v / acc;
+    return OMC_OK;
+}
+
+// One beam of a job on the host. Spectra are shared between beams by pointer.
+struct HostBeam {
+    omc_source src;                     // spectrum pointers unused
+    const std::vector<double>* edges;   // n_bins + 1
+    const std::vector<double>* cdf;     // n_bins
+    uint64_t n;
+    uint32_t h0;
+};
+
+struct Job {
+    std::vector<HostBeam> beams;
+    int particle = 0;
+    int cell_mode = 0;  // 0: cells are batches of the history range; 1: cells are beams
+    int cells = 1;
+    uint64_t N = 0;
+};
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Lay the job's beams out in device memory (one upload, asynchronous on s; the
+// host copy stays alive in the context until the run has synchronised).
 template <typename R>
-int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose, double* d_dose2,
-             hipStream_t s)
+int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& v)
+{
+    const size_t nb = job.beams.size();
+    std::vector<omc::BeamSrc<R>> bs(nb);
+    std::vector<uint64_t> first(nb + 1, 0);
+    std::vector<double> cdf;
+    std::vector<R> edges;
+    const std::vector<double>* last = nullptr;
+    int last_c = 0, last_e = 0;
+    for (size_t b = 0; b < nb; ++b) {
+        const HostBeam& hb = job.beams[b];
+        const omc_source& sr = hb.src;
+        omc::BeamSrc<R>& o = bs[b];
+        std::memset(&o, 0, sizeof o);
+        o.mono_E = R(sr.mono_E);
+        o.ssd = R(sr.ssd);
+        o.z_field = R(sr.z_field);
+        o.fx = R(sr.fx);
+        o.fy = R(sr.fy);
+        o.cx = R(sr.cx);
+        o.cy = R(sr.cy);
+        o.sx = R(sr.sx);
+        o.sy = R(sr.sy);
+        const double gr = sr.gantry_deg * omc::kPi / 180.0;
+        o.cg = R(std::cos(gr));
+        o.sg = R(std::sin(gr));
+        o.iso_x = R(sr.iso_x);
+        o.iso_z = R(sr.iso_z);
+        o.n_bins = sr.n_bins;
+        o.point = sr.geometry == 1;
+        o.rotate = sr.gantry_deg != 0.0;
+        o.h0 = hb.h0;
+        if (sr.n_bins > 0) {
+            if (hb.edges != last) {
+                last = hb.edges;
+                last_c = int(cdf.size());
+                last_e = int(edges.size());
+                cdf.insert(cdf.end(), hb.cdf->begin(), hb.cdf->end());
+                for (double e : *hb.edges) edges.push_back(R(e));
+            }
+            o.cdf_off = last_c;
+            o.edge_off = last_e;
+        }
+        first[b + 1] = first[b] + hb.n;
+    }
+    const size_t o_beams = 0;
+    const size_t o_first = o_beams + align256(nb * sizeof(omc::BeamSrc<R>));
+    const size_t o_cdf = o_first + align256((nb + 1) * sizeof(uint64_t));
+    const size_t o_edges = o_cdf + align256(std::max<size_t>(cdf.size(), 1) * sizeof(double));
+    const size_t total = o_edges + align256(std::max<size_t>(edges.size(), 1) * sizeof(R));
+    if (c->src_cap < total) {
+        dfree(c->d_src);
+        c->src_cap = 0;
+        const size_t want = std::max<size_t>(total, 64 * 1024);
+        if (hipMalloc(&c->d_src, want) != hipSuccess) {
+            c->d_src = nullptr;
+            return fail(c, OMC_ENOMEM, "hipMalloc failed for the source description");
+        }
+        c->src_cap = want;
+    }
+    c->src_stage.assign(total, 0);
+    char* h = c->src_stage.data();
+    std::memcpy(h + o_beams, bs.data(), nb * sizeof(omc::BeamSrc<R>));
+    std::memcpy(h + o_first, first.data(), (nb + 1) * sizeof(uint64_t));
+    if (!cdf.empty()) std::memcpy(h + o_cdf, cdf.data(), cdf.size() * sizeof(double));
+    if (!edges.empty()) std::memcpy(h + o_edges, edges.data(), edges.size() * sizeof(R));
+    HIP_TRY(c, hipMemcpyAsync(c->d_src, h, total, hipMemcpyHostToDevice, s));
+    v.beams = reinterpret_cast<const omc::BeamSrc<R>*>(c->d_src + o_beams);
+    v.first = reinterpret_cast<const uint64_t*>(c->d_src + o_first);
+    v.cdf = reinterpret_cast<const double*>(c->d_src + o_cdf);
+    v.edges = reinterpret_cast<const R*>(c->d_src + o_edges);
+    v.n_beams = int(nb);
+    v.particle = job.particle;
+    v.cell_mode = job.cell_mode;
+    return OMC_OK;
+}
+
+// ----------------------------------------------------------------- transport
+// Transport every history of the job into the cell grids; the statistics stay
+// on the device (finish_stats reads them). L.iterations counts generations.
+template <typename R>
+int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTimer& tm,
+              omc_counters& L)
 {
     DeviceTables<R>& T = tables_of(c, R());
     DeviceQueues<R>& Q = queues_of(c, R());
     int rc = device_tables(c, T);
     if (rc) return rc;
     const omc_params& P = c->prm;
-    const int B = P.n_batches;
-    const uint64_t chunk =
-        P.chunk_histories > 0 ? uint64_t(P.chunk_histories) : std::min<uint64_t>(N, uint64_t(1) << 24);
-    const uint64_t S = std::min<uint64_t>(chunk, N);
+    const uint64_t N = job.N;
+    const uint64_t S = std::min<uint64_t>(
+        P.chunk_histories > 0 ? uint64_t(P.chunk_histories) : (uint64_t(1) << 24), N);
     // capacity: secondaries per source history, plus the holes left by the
     // per-wave slot reservations of the two kernels that append to a queue
     const uint64_t waves = uint64_t(c->cu_count) * P.blocks_per_cu * (P.block_size / 64);
@@ -380,36 +619,28 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
         uint64_t(P.queue_factor) * S + 2 * waves * omc::kResBlockSlots + 4096, 0x7fffffffull);
     if ((rc = ensure_queues(c, Q, uint32_t(std::max<uint64_t>(qcap, S)), uint32_t(qcap)))) return rc;
 
-    // tally grids
-    const size_t need = size_t(B) * c->nvox;
-    if (c->grid_batches < size_t(B)) {
+    const size_t need = size_t(job.cells) * c->nvox;
+    if (c->grid_cells < size_t(job.cells)) {
+        drop_graph(c);
         dfree(c->d_grid);
+        c->grid_cells = 0;
         if (hipMalloc(&c->d_grid, need * sizeof(double)) != hipSuccess) {
             c->d_grid = nullptr;
-            c->grid_batches = 0;
-            return fail(c, OMC_ENOMEM, "hipMalloc failed for the batch dose grids");
+            return fail(c, OMC_ENOMEM, "hipMalloc failed for the tally grids");
         }
-        c->grid_batches = size_t(B);
+        c->grid_cells = size_t(job.cells);
     }
-    // source spectrum edges in the transport precision
-    if (c->src.n_bins > 0 && !T.edges) {
-        std::vector<R> e(c->edges.begin(), c->edges.end());
-        if ((rc = upload(c, T.edges, e))) return rc;
-    }
+    // launch checks read the runtime's last error: start from a clean state
+    (void)hipGetLastError();
+    omc::SourceView<R> sv{};
+    if ((rc = pack_sources(c, job, s, sv))) return rc;
+    c->h_run->seed = seed;
+    c->h_run->n_batches = job.cell_mode ? 0u : uint32_t(job.cells);
+    c->h_run->n_total = N;
+    HIP_TRY(c, hipMemcpyAsync(c->d_run, c->h_run, sizeof(omc::RunDesc), hipMemcpyHostToDevice, s));
 
-    EventTimer tm;
-    tm.on = P.timing != 0;
-    tm.s = s;
-
-    HIP_TRY(c, hipMemsetAsync(c->d_grid, 0, need * sizeof(double), s));
-    HIP_TRY(c, hipMemsetAsync(c->d_counters, 0,
-                              size_t(omc::kStatsRows) * omc::kNumCounters *
-                                  sizeof(unsigned long long), s));
-    HIP_TRY(c, hipMemsetAsync(c->d_energies, 0,
-                              size_t(omc::kStatsRows) * omc::kNumEnergies * sizeof(double), s));
-    HIP_TRY(c, hipMemsetAsync(c->d_ctrl, 0, 16 * sizeof(uint32_t), s));
-
-    omc::KernelArgs<R> a{};
+    omc::KernelArgs<R> a;
+    std::memset(&a, 0, sizeof a);
     a.ph = {c->d_rho, c->d_mat, c->nx, c->ny, c->nz, R(c->dx), R(c->dy), R(c->dz),
             R(1.0 / c->dx), R(1.0 / c->dy), R(1.0 / c->dz)};
     const omc::EnergyGrid g = omc::energy_grid();
@@ -433,41 +664,17 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     const double skin = 1e-3 * std::fmin(c->dx, std::fmin(c->dy, c->dz));
     a.prm = {R(P.Eabs_e), R(P.Eabs_g), R(P.Wcc), R(P.kc), R(P.dmax_s), R(1.0 - P.f_E), R(skin),
              P.kerma_mode, P.csda_mode};
-    a.tally = {c->d_grid, c->nvox, N, h0, B};
-    a.stats = {c->d_counters, c->d_energies, omc::kStatsRows, c->d_ctrl + 8, c->d_ctrl + 9};
-    const omc_source& sr = c->src;
-    a.src.cdf = c->d_cdf;
-    a.src.edges = T.edges;
-    a.src.n_bins = sr.n_bins;
-    a.src.particle = sr.particle;
-    a.src.point = sr.geometry == 1;
-    a.src.mono_E = R(sr.mono_E);
-    a.src.ssd = R(sr.ssd);
-    a.src.z_field = R(sr.z_field);
-    a.src.fx = R(sr.fx);
-    a.src.fy = R(sr.fy);
-    a.src.cx = R(sr.cx);
-    a.src.cy = R(sr.cy);
-    a.src.sx = R(sr.sx);
-    a.src.sy = R(sr.sy);
-    a.src.rotate = sr.gantry_deg != 0.0;
-    const double gr = sr.gantry_deg * omc::kPi / 180.0;
-    a.src.cg = R(std::cos(gr));
-    a.src.sg = R(std::sin(gr));
-    a.src.iso_x = R(sr.iso_x);
-    a.src.iso_z = R(sr.iso_z);
+    a.tally = {c->d_grid, c->nvox};
+    a.stats = {c->d_counters, c->d_energies, omc::kStatsRows, c->d_ctrl + 8, c->d_ctrl + 9,
+               c->d_ctrl + 10};
+    a.src = sv;
     a.trace = c->trace;
-    a.seed = seed;
+    a.run = c->d_run;
     a.chunk = 64;
+    a.min_grid = c->cu_count;
 
     const int block = P.block_size;
     const int tgrid = c->cu_count * P.blocks_per_cu;
-    // a generation with few records needs fewer persistent work-groups: about
-    // two records per lane, never fewer than one work-group per CU
-    auto grid_for = [&](uint32_t n_records) {
-        const uint64_t want = (uint64_t(n_records) + 2ull * block - 1) / (2ull * block);
-        return int(std::max<uint64_t>(c->cu_count, std::min<uint64_t>(want, uint64_t(tgrid))));
-    };
     const int nm = int(c->mats.size());
     const size_t lds_ph = omc::photon_lds_bytes<R>(nm);
     const size_t lds_el = omc::electron_lds_bytes<R>(nm);
@@ -476,69 +683,167 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     if (lds_ph > size_t(lds_max) || lds_el > size_t(lds_max))
         return fail(c, OMC_EUNSUP, "material tables exceed the LDS of a work-group; use fewer "
                                    "materials (or the FP32 build)");
+    if (omc::Launch<R>::prepare(lds_ph, lds_el))
+        return fail(c, OMC_EDEVICE, "cannot raise the LDS limit of the transport kernels");
 
-    omc_counters& L = c->last;
-    L = omc_counters{};
-    uint32_t iters = 0;
-    for (uint64_t done = 0; done < N; done += S) {
-        const uint32_t cnt = uint32_t(std::min<uint64_t>(S, N - done));
-        int pc = 0, ec = 2;  // current photon / electron buffers
+    auto zero_all = [&](hipStream_t st) {
+        return omc::launch_zero(c->d_grid, need, st) ||
+               omc::launch_zero(c->d_counters, size_t(omc::kStatsRows) * omc::kNumCounters, st) ||
+               omc::launch_zero(c->d_energies, size_t(omc::kStatsRows) * omc::kNumEnergies, st) ||
+               omc::launch_zero(c->d_ctrl, 8, st);
+    };
+    auto source = [&](uint64_t begin, uint32_t cnt, int pc, int ec, hipStream_t st,
+                      EventTimer& t) {
         a.qp_out = Q.q[pc];
         a.qe_out = Q.q[ec];
-        a.src_begin = uint32_t(done);
+        a.src_begin = begin;
         a.src_count = cnt;
-        tm.begin(0);
-        if (omc::Launch<R>::source(a, int((cnt + 255) / 256), 256, s))
-            return fail(c, OMC_EDEVICE, "source kernel launch failed");
-        tm.end();
-        uint32_t n_ph = sr.particle == 0 ? cnt : 0, n_el = sr.particle == 0 ? 0 : cnt;
-        for (;;) {
-            if (++iters > 100000) return fail(c, OMC_ENUMERIC, "generation limit exceeded");
-            if (n_ph) {
-                a.qin = Q.q[pc];
-                a.qe_out = Q.q[ec];
-                a.qp_out = Q.q[pc ^ 1];
-                tm.begin(1);
-                if (omc::Launch<R>::photon(a, grid_for(n_ph), block, lds_ph, s))
-                    return fail(c, OMC_EDEVICE, "photon kernel launch failed");
-                tm.end();
-            }
-            // electrons created by the photon kernel are in Q.q[ec]; their count
-            // is known on the host only when no photon kernel ran before
-            a.qin = Q.q[ec];
-            a.qe_out = Q.q[ec ^ 1];
+        t.begin(0);
+        const int e = omc::Launch<R>::source(a, int((cnt + 255) / 256), 256, st);
+        t.end();
+        return e || omc::launch_queue_commit(c->d_ctrl, job.particle == 0 ? pc : ec, cnt, st);
+    };
+    auto generation = [&](int pc, int ec, bool photons, hipStream_t st, EventTimer& t) {
+        int e = 0;
+        if (photons) {
+            a.qin = Q.q[pc];
+            a.qe_out = Q.q[ec];
             a.qp_out = Q.q[pc ^ 1];
-            tm.begin(2);
-            if (omc::Launch<R>::electron(a, n_ph ? tgrid : grid_for(n_el), block, lds_el, s))
-                return fail(c, OMC_EDEVICE, "electron kernel launch failed");
-            tm.end();
-            if (omc::launch_queue_reset(c->d_ctrl, (1 << pc) | (1 << ec), s))
-                return fail(c, OMC_EDEVICE, "queue reset launch failed");
+            t.begin(1);
+            e = omc::Launch<R>::photon(a, tgrid, block, lds_ph, st);
+            t.end();
+        }
+        a.qin = Q.q[ec];
+        a.qe_out = Q.q[ec ^ 1];
+        a.qp_out = Q.q[pc ^ 1];
+        t.begin(2);
+        e = e || omc::Launch<R>::electron(a, tgrid, block, lds_el, st);
+        t.end();
+        return e || omc::launch_queue_reset(c->d_ctrl, (1 << pc) | (1 << ec), st);
+    };
+    uint32_t iters = 0;
+    auto readback = [&](int pc, int ec, uint32_t& n_ph, uint32_t& n_el) -> int {
+        HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 16 * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (c->h_ctrl[8])
+            return fail(c, OMC_EQUEUE,
+                        "secondary particle queue overflow; raise queue_factor or lower "
+                        "chunk_histories");
+        n_ph = c->h_ctrl[2 * pc];
+        n_el = c->h_ctrl[2 * ec];
+        return OMC_OK;
+    };
+    // host-driven generations until both queues are empty
+    auto drain = [&](int& pc, int& ec, uint32_t n_ph, uint32_t n_el) -> int {
+        while (n_ph || n_el) {
+            if (++iters > 100000) return fail(c, OMC_ENUMERIC, "generation limit exceeded");
+            if (generation(pc, ec, n_ph != 0, s, tm))
+                return fail(c, OMC_EDEVICE, "transport kernel launch failed");
             pc ^= 1;
             ec ^= 1;
-            HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 16 * sizeof(uint32_t),
-                                      hipMemcpyDeviceToHost, s));
-            HIP_TRY(c, hipStreamSynchronize(s));
-            if (c->h_ctrl[8]) {
-                tm.collect(c->timing);
-                return fail(c, OMC_EQUEUE,
-                            "secondary particle queue overflow; raise queue_factor or lower "
-                            "chunk_histories");
-            }
-            n_ph = c->h_ctrl[2 * pc];
-            n_el = c->h_ctrl[2 * ec];
-            L.queue_hwm_ph = std::max<uint64_t>(L.queue_hwm_ph, n_ph);
-            L.queue_hwm_el = std::max<uint64_t>(L.queue_hwm_el, n_el);
-            if (n_ph == 0 && n_el == 0) break;
+            const int e = readback(pc, ec, n_ph, n_el);
+            if (e) return e;
         }
+        return OMC_OK;
+    };
+
+    int pc = 0, ec = 2;  // current photon / electron queues
+    if (P.graph_depth > 0 && P.timing) {
+        // HIP events do not time kernels inside a graph: the timed variant
+        // launches the same fixed-depth sequence eagerly, one event pair per
+        // launch (same kernels, same grids, same carry-over)
+        if (zero_all(s)) return fail(c, OMC_EDEVICE, "zero-fill launch failed");
+        for (uint64_t done = 0; done < N; done += S) {
+            const uint32_t cnt = uint32_t(std::min<uint64_t>(S, N - done));
+            if (source(done, cnt, pc, ec, s, tm))
+                return fail(c, OMC_EDEVICE, "source kernel launch failed");
+            for (int k = 0; k < P.graph_depth; ++k, ++iters) {
+                if (generation(pc, ec, true, s, tm))
+                    return fail(c, OMC_EDEVICE, "transport kernel launch failed");
+                pc ^= 1;
+                ec ^= 1;
+            }
+        }
+        uint32_t n_ph = 0, n_el = 0;
+        if ((rc = readback(pc, ec, n_ph, n_el))) return rc;
+        if ((rc = drain(pc, ec, n_ph, n_el))) return rc;
+    } else if (P.graph_depth <= 0) {
+        if (zero_all(s)) return fail(c, OMC_EDEVICE, "zero-fill launch failed");
+        for (uint64_t done = 0; done < N; done += S) {
+            const uint32_t cnt = uint32_t(std::min<uint64_t>(S, N - done));
+            if (source(done, cnt, pc, ec, s, tm))
+                return fail(c, OMC_EDEVICE, "source kernel launch failed");
+            // the queues were drained before this chunk
+            if ((rc = drain(pc, ec, job.particle == 0 ? cnt : 0, job.particle == 0 ? 0 : cnt)))
+                return rc;
+        }
+    } else {
+        const int K = P.graph_depth;
+        // everything the captured launches depend on; a change means a new capture
+        std::vector<unsigned char> key(sizeof a + 16 * sizeof(uint64_t));
+        const uint64_t shape[16] = {sizeof(R), N,      S,      uint64_t(K), uint64_t(block),
+                                    uint64_t(tgrid),   lds_ph, lds_el,      uint64_t(P.timing),
+                                    uint64_t(job.particle), need, 0, 0, 0, 0, 0};
+        std::memcpy(key.data(), &a, sizeof a);
+        std::memcpy(key.data() + sizeof a, shape, sizeof shape);
+        if (!c->graph || key != c->graph_key) {
+            drop_graph(c);
+            if (!c->cap_stream &&
+                hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+                c->cap_stream = nullptr;
+                return fail(c, OMC_EDEVICE, "cannot create the capture stream");
+            }
+            EventTimer gt;  // not recording: events cannot time kernels inside a graph
+            gt.s = c->cap_stream;
+            HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            int e = zero_all(c->cap_stream);
+            int gpc = 0, gec = 2;
+            uint32_t giters = 0;
+            for (uint64_t done = 0; done < N && !e; done += S) {
+                const uint32_t cnt = uint32_t(std::min<uint64_t>(S, N - done));
+                e = source(done, cnt, gpc, gec, c->cap_stream, gt);
+                for (int k = 0; k < K && !e; ++k) {
+                    e = generation(gpc, gec, true, c->cap_stream, gt);
+                    gpc ^= 1;
+                    gec ^= 1;
+                    ++giters;
+                }
+            }
+            hipGraph_t gr = nullptr;
+            const hipError_t ce = hipStreamEndCapture(c->cap_stream, &gr);
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ie = (e || ce != hipSuccess || !gr)
+                                      ? hipErrorUnknown
+                                      : hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            if (gr) (void)hipGraphDestroy(gr);
+            if (e || ce != hipSuccess || ie != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, OMC_EDEVICE, std::string("graph capture failed: ") +
+                                                hipGetErrorString(ce != hipSuccess ? ce : ie));
+            }
+            c->graph = ex;
+            c->graph_key = key;
+            c->graph_pc = gpc;
+            c->graph_ec = gec;
+            c->graph_iters = giters;
+        }
+        HIP_TRY(c, hipGraphLaunch(c->graph, s));
+        iters += c->graph_iters;
+        pc = c->graph_pc;
+        ec = c->graph_ec;
+        uint32_t n_ph = 0, n_el = 0;
+        if ((rc = readback(pc, ec, n_ph, n_el))) return rc;
+        if ((rc = drain(pc, ec, n_ph, n_el))) return rc;
     }
-    std::vector<double> nb;
-    batch_sizes(N, B, nb);
-    tm.begin(3);
-    if (omc::launch_fold(c->d_grid, c->d_rho, c->nvox, B, nb.data(), c->dx * c->dy * c->dz,
-                         double(N), d_dose, d_dose2, s))
-        return fail(c, OMC_EDEVICE, "fold kernel launch failed");
-    tm.end();
+    L.iterations += iters;
+    return OMC_OK;
+}
+
+// Sum the per-work-group statistics and read them (and the control words)
+// into L; accumulate adds to what L holds.
+int finish_stats(omc_ctx* c, hipStream_t s, omc_counters& L, bool accumulate)
+{
     unsigned long long cnts[omc::kNumCounters];
     double en[omc::kNumEnergies];
     if (omc::launch_stats_reduce(c->d_counters, c->d_energies, omc::kStatsRows, s))
@@ -548,15 +853,25 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     HIP_TRY(c, hipMemcpyAsync(cnts, c->d_counters, sizeof cnts, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(en, c->d_energies, sizeof en, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    tm.collect(c->timing);
-    for (int k = 0; k < omc::kNumCounters; ++k) L.*kCounterField[k] = cnts[k];
-    L.E_incident = en[omc::EN_INCIDENT];
-    L.E_deposited = en[omc::EN_DEPOSITED];
-    L.E_escaped = en[omc::EN_ESCAPED];
+    if (!accumulate) {
+        const uint32_t it = L.iterations;
+        L = omc_counters{};
+        L.iterations = it;
+    }
+    for (int k = 0; k < omc::kNumCounters; ++k) L.*kCounterField[k] += cnts[k];
+    L.E_incident += en[omc::EN_INCIDENT];
+    L.E_deposited += en[omc::EN_DEPOSITED];
+    L.E_escaped += en[omc::EN_ESCAPED];
     L.E_pair_rest = double(L.ph_pair) * 2.0 * omc::kMC2;
     L.E_annih_rest = double(L.pos_annihil) * 2.0 * omc::kMC2;
-    L.iterations = iters;
-    L.max_steps = c->h_ctrl[9];
+    L.max_steps = std::max(L.max_steps, c->h_ctrl[9]);
+    L.queue_hwm_el = std::max<uint64_t>(L.queue_hwm_el, c->h_ctrl[10]);
+    L.queue_hwm_ph = std::max<uint64_t>(L.queue_hwm_ph, c->h_ctrl[11]);
+    return OMC_OK;
+}
+
+int check_ledger(omc_ctx* c, const omc_counters& L)
+{
     const double lhs = L.E_incident + L.E_annih_rest - L.E_pair_rest;
     const double rhs = L.E_deposited + L.E_escaped;
     if (!std::isfinite(lhs) || !std::isfinite(rhs) || std::fabs(lhs - rhs) > 1e-9 * std::fabs(lhs))
@@ -565,7 +880,243 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     return OMC_OK;
 }
 
+template <typename R>
+int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose, double* d_dose2,
+             hipStream_t s)
+{
+    const omc_params& P = c->prm;
+    Job job;
+    job.beams.push_back(HostBeam{c->src, &c->edges, &c->cdf, N, h0});
+    job.particle = c->src.particle;
+    job.cell_mode = 0;
+    job.cells = P.n_batches;
+    job.N = N;
+    c->timing = omc_timing{};
+    EventTimer tm;
+    tm.on = P.timing != 0;
+    tm.s = s;
+    RunClock clk;
+    clk.start(tm.on, s);
+    omc_counters& L = c->last;
+    L = omc_counters{};
+    int rc = transport<R>(c, job, seed, s, tm, L);
+    if (rc == OMC_OK) {
+        std::vector<double> nb;
+        batch_sizes(N, job.cells, nb);
+        tm.begin(3);
+        if (omc::launch_fold(c->d_grid, c->d_rho, c->nvox, job.cells, nb.data(),
+                             c->dx * c->dy * c->dz, double(N), d_dose, d_dose2, s))
+            rc = fail(c, OMC_EDEVICE, "fold kernel launch failed");
+        tm.end();
+        clk.stop(s);
+        if (rc == OMC_OK) rc = finish_stats(c, s, L, false);
+    }
+    (void)hipStreamSynchronize(s);
+    collect_events(tm.ev, c->timing);
+    destroy_events(tm.ev);
+    clk.collect(c->timing);
+    if (rc) return rc;
+    return check_ledger(c, L);
+}
 
+// ------------------------------------------------------------------ beamlets
+struct SparsePart {
+    uint32_t* voxel = nullptr;
+    float* dose = nullptr;
+    uint64_t nnz = 0;
+};
+
+void free_parts(std::vector<SparsePart>& parts)
+{
+    for (auto& p : parts) {
+        dfree(p.voxel);
+        dfree(p.dose);
+    }
+    parts.clear();
+}
+
+int ensure_cscratch(omc_ctx* c, size_t bytes)
+{
+    if (c->cscratch_cap >= bytes) return OMC_OK;
+    dfree(c->d_cscratch);
+    c->cscratch_cap = 0;
+    if (hipMalloc(&c->d_cscratch, bytes) != hipSuccess) {
+        c->d_cscratch = nullptr;
+        return fail(c, OMC_ENOMEM, "hipMalloc failed for the compaction scratch");
+    }
+    c->cscratch_cap = bytes;
+    return OMC_OK;
+}
+
+// Compact the cell grids of one group of beams into device CSR arrays; rows
+// receives the group's n_beams + 1 row offsets (starting at 0).
+int compact_group(omc_ctx* c, const Job& job, hipStream_t s, EventTimer& tm, SparsePart& part,
+                  std::vector<uint64_t>& rows)
+{
+    const int G = job.cells;
+    const size_t tiles = (c->nvox + omc::kCompactTile - 1) / omc::kCompactTile;
+    const size_t nt = size_t(G) * tiles;
+    const size_t n_seg = (nt + 1023) / 1024;
+    const size_t o_scale = 0;
+    const size_t o_thr = o_scale + align256(size_t(G) * sizeof(double));
+    const size_t o_cnt = o_thr + align256(size_t(G) * sizeof(float));
+    const size_t o_off = o_cnt + align256(nt * sizeof(uint32_t));
+    const size_t o_tmp = o_off + align256((nt + 1) * sizeof(uint64_t));
+    const size_t bytes = o_tmp + align256((n_seg + 1) * sizeof(uint64_t));
+    int rc = ensure_cscratch(c, bytes);
+    if (rc) return rc;
+    double* d_scale = reinterpret_cast<double*>(c->d_cscratch + o_scale);
+    float* d_thr = reinterpret_cast<float*>(c->d_cscratch + o_thr);
+    uint32_t* d_cnt = reinterpret_cast<uint32_t*>(c->d_cscratch + o_cnt);
+    uint64_t* d_off = reinterpret_cast<uint64_t*>(c->d_cscratch + o_off);
+    uint64_t* d_tmp = reinterpret_cast<uint64_t*>(c->d_cscratch + o_tmp);
+
+    const double V = c->dx * c->dy * c->dz;
+    std::vector<double> scale(G);
+    for (int b = 0; b < G; ++b) scale[b] = 1.0 / (V * double(job.beams[b].n));
+    HIP_TRY(c, hipMemcpyAsync(d_scale, scale.data(), G * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemsetAsync(d_thr, 0, G * sizeof(float), s));
+    const double thr_rel = c->prm.sparse_threshold;
+    std::vector<float> mx(G);  // host memory of an asynchronous copy: alive until the sync below
+    tm.begin(3);
+    if (thr_rel > 0) {
+        if (omc::launch_beam_max(c->d_grid, c->d_rho, c->nvox, G, d_scale, d_thr, s))
+            return fail(c, OMC_EDEVICE, "beam maximum launch failed");
+        HIP_TRY(c, hipMemcpyAsync(mx.data(), d_thr, G * sizeof(float), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        for (float& m : mx) m = float(double(m) * thr_rel);
+        HIP_TRY(c, hipMemcpyAsync(d_thr, mx.data(), G * sizeof(float), hipMemcpyHostToDevice, s));
+    }
+    if (omc::launch_compact_count(c->d_grid, c->d_rho, c->nvox, G, d_scale, d_thr, d_cnt, s) ||
+        omc::launch_scan(d_cnt, d_off, nt, d_tmp, s))
+        return fail(c, OMC_EDEVICE, "compaction count/scan launch failed");
+    tm.end();
+    // row b starts at the offset of its first tile; the last row ends at the total
+    rows.assign(size_t(G) + 1, 0);
+    HIP_TRY(c, hipMemcpy2DAsync(rows.data(), sizeof(uint64_t), d_off, tiles * sizeof(uint64_t),
+                                sizeof(uint64_t), size_t(G) + 1, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    part.nnz = rows[G];
+    if (part.nnz == 0) return OMC_OK;
+    if (hipMalloc(&part.voxel, part.nnz * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&part.dose, part.nnz * sizeof(float)) != hipSuccess) {
+        dfree(part.voxel);
+        dfree(part.dose);
+        return fail(c, OMC_ENOMEM, "hipMalloc failed for the sparse dose rows");
+    }
+    tm.begin(3);
+    if (omc::launch_compact_write(c->d_grid, c->d_rho, c->nvox, G, d_scale, d_thr, d_off,
+                                  part.nnz, part.voxel, part.dose, s))
+        return fail(c, OMC_EDEVICE, "compaction write launch failed");
+    tm.end();
+    return OMC_OK;
+}
+
+template <typename R>
+int beamlets_impl(omc_ctx* c, const std::vector<HostBeam>& beams, int particle, uint32_t seed,
+                  int on_device, hipStream_t s, omc_sparse_out* out)
+{
+    const omc_params& P = c->prm;
+    const int n = int(beams.size());
+    const size_t tiles = (c->nvox + omc::kCompactTile - 1) / omc::kCompactTile;
+    int G = P.beamlet_group > 0 ? std::min(P.beamlet_group, n) : 0;
+    if (G == 0) {
+        size_t freeb = 0, totalb = 0;
+        HIP_TRY(c, hipMemGetInfo(&freeb, &totalb));
+        const size_t per = c->nvox * sizeof(double);
+        const size_t budget = freeb / 2 + c->grid_cells * per;
+        G = int(std::max<size_t>(1, std::min<size_t>(size_t(n), budget / per)));
+    }
+    // cell ids fit the 24 bits of a record tag, the compaction grid and the scan
+    G = std::min(G, 65535);
+    while (G > 1 && size_t(G) * tiles > (size_t(1) << 31)) G /= 2;
+
+    c->timing = omc_timing{};
+    EventTimer tm;
+    tm.on = P.timing != 0;
+    tm.s = s;
+    RunClock clk;
+    clk.start(tm.on, s);
+    omc_counters& L = c->last;
+    L = omc_counters{};
+    std::vector<SparsePart> parts;
+    std::vector<uint64_t> rows(size_t(n) + 1, 0);
+    int rc = OMC_OK;
+    for (int g0 = 0; g0 < n && rc == OMC_OK; g0 += G) {
+        const int gn = std::min(G, n - g0);
+        Job job;
+        job.beams.assign(beams.begin() + g0, beams.begin() + g0 + gn);
+        job.particle = particle;
+        job.cell_mode = 1;
+        job.cells = gn;
+        for (const auto& b : job.beams) job.N += b.n;
+        rc = transport<R>(c, job, seed, s, tm, L);
+        SparsePart part;
+        std::vector<uint64_t> grows;
+        if (rc == OMC_OK) rc = compact_group(c, job, s, tm, part, grows);
+        if (rc == OMC_OK) rc = finish_stats(c, s, L, g0 > 0);
+        if (rc == OMC_OK) {
+            const uint64_t base = rows[g0];
+            for (int b = 0; b < gn; ++b) rows[g0 + b + 1] = base + grows[b + 1];
+        }
+        parts.push_back(part);
+    }
+    clk.stop(s);
+    (void)hipStreamSynchronize(s);
+    collect_events(tm.ev, c->timing);
+    destroy_events(tm.ev);
+    clk.collect(c->timing);
+    if (rc == OMC_OK) rc = check_ledger(c, L);
+    if (rc) {
+        free_parts(parts);
+        return rc;
+    }
+    // assemble the rows of all groups
+    const uint64_t nnz = rows[n];
+    out->n_beamlets = n;
+    out->on_device = on_device;
+    out->nnz = nnz;
+    out->row_ptr = static_cast<uint64_t*>(std::malloc((size_t(n) + 1) * sizeof(uint64_t)));
+    if (!out->row_ptr) {
+        free_parts(parts);
+        return fail(c, OMC_ENOMEM, "host allocation failed for the row offsets");
+    }
+    std::memcpy(out->row_ptr, rows.data(), (size_t(n) + 1) * sizeof(uint64_t));
+    if (nnz == 0) {
+        free_parts(parts);
+        return OMC_OK;
+    }
+    if (on_device && parts.size() == 1) {
+        out->voxel = parts[0].voxel;
+        out->dose = parts[0].dose;
+        parts[0] = SparsePart{};
+        return OMC_OK;
+    }
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (on_device) {
+        if (hipMalloc(&out->voxel, nnz * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&out->dose, nnz * sizeof(float)) != hipSuccess)
+            rc = fail(c, OMC_ENOMEM, "hipMalloc failed for the sparse dose rows");
+    } else {
+        out->voxel = static_cast<uint32_t*>(std::malloc(nnz * sizeof(uint32_t)));
+        out->dose = static_cast<float*>(std::malloc(nnz * sizeof(float)));
+        if (!out->voxel || !out->dose)
+            rc = fail(c, OMC_ENOMEM, "host allocation failed for the sparse dose rows");
+    }
+    uint64_t at = 0;
+    for (const auto& p : parts) {
+        if (rc || p.nnz == 0) continue;
+        if (hipMemcpyAsync(out->voxel + at, p.voxel, p.nnz * sizeof(uint32_t), kind, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(out->dose + at, p.dose, p.nnz * sizeof(float), kind, s) != hipSuccess)
+            rc = fail(c, OMC_EDEVICE, "copy of the sparse dose rows failed");
+        at += p.nnz;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == OMC_OK)
+        rc = fail(c, OMC_EDEVICE, "copy of the sparse dose rows failed");
+    free_parts(parts);
+    return rc;
+}
 
 }  // namespace
 
@@ -590,6 +1141,9 @@ void omc_default_params(omc_params* p)
     p->chunk_histories = 0;
     p->queue_factor = 6;
     p->timing = 0;
+    p->graph_depth = 0;
+    p->beamlet_group = 0;
+    p->sparse_threshold = 0.0;
 }
 
 int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
@@ -654,7 +1208,9 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
                                             sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc(&c->d_energies, size_t(omc::kStatsRows) * omc::kNumEnergies *
                                             sizeof(double)) == hipSuccess &&
-              hipHostMalloc(&c->h_ctrl, 64 * sizeof(uint32_t)) == hipSuccess;
+              hipHostMalloc(&c->h_ctrl, 64 * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc(&c->d_run, sizeof(omc::RunDesc)) == hipSuccess &&
+              hipHostMalloc(&c->h_run, sizeof(omc::RunDesc)) == hipSuccess;
     ok = ok && hipMemcpy(c->d_rho, c->rho.data(), c->nvox * sizeof(float), hipMemcpyHostToDevice) ==
                    hipSuccess;
     ok = ok && hipMemcpy(c->d_mat, c->mat.data(), c->nvox, hipMemcpyHostToDevice) == hipSuccess;
@@ -669,51 +1225,14 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
 int omc_set_source(omc_ctx* c, const omc_source* s)
 {
     if (check_ctx(c) || !s) return fail(c, OMC_EINVAL, "NULL argument");
-    if (s->particle != 0 && s->particle != 1) return fail(c, OMC_EINVAL, "particle must be 0 or 1");
-    if (s->geometry != 0 && s->geometry != 1) return fail(c, OMC_EINVAL, "geometry must be 0 or 1");
-    if (!(s->fx > 0) || !(s->fy > 0) || !std::isfinite(s->fx) || !std::isfinite(s->fy))
-        return fail(c, OMC_EINVAL, "field size must be > 0");
-    if (s->geometry == 1 && !finite_pos(s->ssd)) return fail(c, OMC_EINVAL, "ssd must be > 0");
-    const double chk[] = {s->z_field, s->cx, s->cy, s->sx, s->sy, s->gantry_deg, s->iso_x, s->iso_z};
-    for (double v : chk)
-        if (!std::isfinite(v)) return fail(c, OMC_EINVAL, "non-finite source geometry");
-    std::vector<double> edges, weights, cdf;
-    if (s->n_bins < 0 || s->n_bins > 4096) return fail(c, OMC_EINVAL, "n_bins out of range");
-    if (s->n_bins == 0) {
-        if (!(s->mono_E > 0) || !(s->mono_E < omc::kEHi))
-            return fail(c, OMC_EINVAL, "mono_E must be in (0, 20) MeV");
-    } else {
-        if (!s->edges || !s->weights) return fail(c, OMC_EINVAL, "spectrum arrays are NULL");
-        edges.assign(s->edges, s->edges + s->n_bins + 1);
-        weights.assign(s->weights, s->weights + s->n_bins);
-        for (int b = 0; b <= s->n_bins; ++b)
-            if (!(edges[b] > 0) || !(edges[b] < omc::kEHi) || (b && !(edges[b] > edges[b - 1])))
-                return fail(c, OMC_EINVAL, "spectrum edges must increase within (0, 20) MeV");
-        double acc = 0.0;
-        for (int b = 0; b < s->n_bins; ++b) {
-            if (!(weights[b] >= 0) || !std::isfinite(weights[b]))
-                return fail(c, OMC_EINVAL, "spectrum weights must be finite and >= 0");
-            acc += weights[b];
-            cdf.push_back(acc);
-        }
-        if (!(acc > 0)) return fail(c, OMC_EINVAL, "empty spectrum");
-        for (double& v : cdf) v = v / acc;
-    }
-    dfree(c->d_cdf);
-    if (!cdf.empty()) {
-        if (hipMalloc(&c->d_cdf, cdf.size() * sizeof(double)) != hipSuccess)
-            return fail(c, OMC_ENOMEM, "hipMalloc failed for the spectrum");
-        HIP_TRY(c, hipMemcpy(c->d_cdf, cdf.data(), cdf.size() * sizeof(double),
-                             hipMemcpyHostToDevice));
-    }
+    std::vector<double> edges, cdf;
+    std::string why;
+    if (check_source(s, edges, cdf, why) != OMC_OK) return fail(c, OMC_EINVAL, why);
     c->src = *s;
-    c->edges = edges;
-    c->weights = weights;
-    c->cdf = cdf;
     c->src.edges = nullptr;
     c->src.weights = nullptr;
-    dfree(c->t32.edges);
-    dfree(c->t64.edges);
+    c->edges = std::move(edges);
+    c->cdf = std::move(cdf);
     c->has_source = true;
     return OMC_OK;
 }
@@ -731,8 +1250,11 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
     if (p->block_size < 64 || p->block_size > 256 || p->block_size % 64)
         return fail(c, OMC_EINVAL, "block_size must be 64, 128, 192 or 256");
     if (p->blocks_per_cu < 1 || p->blocks_per_cu > 32 || p->queue_factor < 1 ||
-        p->queue_factor > 64 || p->chunk_histories < 0)
+        p->queue_factor > 64 || p->chunk_histories < 0 || p->graph_depth < 0 ||
+        p->graph_depth > 64 || p->beamlet_group < 0 || p->beamlet_group > 65535)
         return fail(c, OMC_EINVAL, "launch shape out of range");
+    if (!(p->sparse_threshold >= 0.0 && p->sparse_threshold < 1.0))
+        return fail(c, OMC_EINVAL, "sparse_threshold must be in [0, 1)");
     c->prm = *p;
     return OMC_OK;
 }
@@ -767,6 +1289,179 @@ int omc_run(omc_ctx* c, uint64_t n, uint32_t seed, uint32_t h0, double* dose, do
     HIP_TRY(c, hipMemcpy(dose, c->d_dose, c->nvox * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(dose2, c->d_dose2, c->nvox * sizeof(double), hipMemcpyDeviceToHost));
     return rc;
+}
+
+int omc_run_beamlets(omc_ctx* c, const omc_beamlet* b, int n_beamlets, uint32_t seed,
+                     int on_device, void* hip_stream, omc_sparse_out* out)
+{
+    if (out) std::memset(out, 0, sizeof *out);
+    if (check_ctx(c) || !b || !out) return fail(c, OMC_EINVAL, "NULL argument");
+    if (n_beamlets < 1 || n_beamlets > 65535)
+        return fail(c, OMC_EINVAL, "need 1 <= n_beamlets <= 65535");
+    // validate every beamlet; spectra given by the same arrays are checked once
+    std::vector<std::vector<double>> edges, cdf;
+    edges.reserve(n_beamlets);
+    cdf.reserve(n_beamlets);
+    std::vector<HostBeam> beams(n_beamlets);
+    const double* last_e = nullptr;
+    const double* last_w = nullptr;
+    int last_n = -1;
+    for (int i = 0; i < n_beamlets; ++i) {
+        const omc_source& s = b[i].src;
+        if (b[i].n_histories == 0 || uint64_t(b[i].h0) + b[i].n_histories > (uint64_t(1) << 32))
+            return fail(c, OMC_EINVAL, "beamlet " + std::to_string(i) +
+                                           ": need n_histories >= 1 and h0 + n <= 2^32");
+        if (s.particle != b[0].src.particle)
+            return fail(c, OMC_EINVAL, "all beamlets must have the same particle type");
+        std::vector<double> e, w;
+        std::string why;
+        if (check_source(&s, e, w, why) != OMC_OK)
+            return fail(c, OMC_EINVAL, "beamlet " + std::to_string(i) + ": " + why);
+        // beamlets that pass the same spectrum arrays share one device copy
+        if (edges.empty() || s.n_bins == 0 || s.edges != last_e || s.weights != last_w ||
+            s.n_bins != last_n) {
+            edges.push_back(std::move(e));
+            cdf.push_back(std::move(w));
+            last_e = s.n_bins ? s.edges : nullptr;
+            last_w = s.n_bins ? s.weights : nullptr;
+            last_n = s.n_bins;
+        }
+        beams[i].src = s;
+        beams[i].src.edges = nullptr;
+        beams[i].src.weights = nullptr;
+        beams[i].edges = &edges.back();
+        beams[i].cdf = &cdf.back();
+        beams[i].n = b[i].n_histories;
+        beams[i].h0 = b[i].h0;
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    return c->prm.parity_fp64
+               ? beamlets_impl<double>(c, beams, b[0].src.particle, seed, on_device != 0, s, out)
+               : beamlets_impl<float>(c, beams, b[0].src.particle, seed, on_device != 0, s, out);
+}
+
+void omc_free_sparse(omc_sparse_out* out)
+{
+    if (!out) return;
+    std::free(out->row_ptr);
+    if (out->on_device) {
+        if (out->voxel) (void)hipFree(out->voxel);
+        if (out->dose) (void)hipFree(out->dose);
+    } else {
+        std::free(out->voxel);
+        std::free(out->dose);
+    }
+    std::memset(out, 0, sizeof *out);
+}
+
+int omc_autotune(omc_ctx* c, uint64_t n_probe, uint32_t seed, omc_params* best)
+{
+    if (check_ctx(c)) return fail(c, OMC_EINVAL, "NULL context");
+    if (!c->has_source) return fail(c, OMC_ESTATE, "omc_set_source must be called first");
+    if (n_probe == 0 || n_probe > (uint64_t(1) << 31))
+        return fail(c, OMC_EINVAL, "need 1 <= n_probe <= 2^31");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!c->d_dose) {
+        if (hipMalloc(&c->d_dose, c->nvox * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->d_dose2, c->nvox * sizeof(double)) != hipSuccess) {
+            dfree(c->d_dose);
+            dfree(c->d_dose2);
+            return fail(c, OMC_ENOMEM, "hipMalloc failed for the dose grids");
+        }
+    }
+    const omc_params base = c->prm;
+    // generations a chunk needs when driven to empty queues from the host
+    auto timed = [&](const omc_params& p, double& ms, omc_counters& L) {
+        c->prm = p;
+        double bestms = 1e300;
+        for (int r = 0; r < 3; ++r) {  // the first run builds tables, queues and graph
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = omc_run_device(c, n_probe, seed, 0, c->d_dose, c->d_dose2, nullptr);
+            const auto t1 = std::chrono::steady_clock::now();
+            if (rc != OMC_OK) return rc;
+            if (r > 0) bestms = std::min(bestms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        ms = bestms;
+        L = c->last;
+        return int(OMC_OK);
+    };
+    struct Shape {
+        int block, per_cu;
+    };
+    const Shape shapes[] = {{256, 2}, {256, 4}, {256, 6}, {256, 8}, {128, 4}, {128, 8}};
+    const uint64_t full = std::min<uint64_t>(n_probe, uint64_t(1) << 24);
+    omc_params top = base;
+    double top_ms = 1e300;
+    uint64_t hwm = 0, hwm_chunk = 1;
+    int last_rc = OMC_OK;
+    for (const Shape& sh : shapes) {
+        omc_params p = base;
+        p.block_size = sh.block;
+        p.blocks_per_cu = sh.per_cu;
+        p.queue_factor = std::max(base.queue_factor, 8);
+        p.timing = 0;
+        // host-driven generations first: they also give the generations per chunk
+        p.graph_depth = 0;
+        p.chunk_histories = int(full);
+        double ms;
+        omc_counters L;
+        int rc = timed(p, ms, L);
+        if (rc != OMC_OK) {
+            last_rc = rc;
+            continue;
+        }
+        const uint64_t chunks = (n_probe + full - 1) / full;
+        const int per_chunk = int(std::min<uint64_t>(64, (L.iterations + chunks - 1) / chunks));
+        std::vector<omc_params> cand;
+        cand.push_back(p);
+        const uint64_t divs[] = {1, 2, 4, 8};
+        for (uint64_t d : divs) {
+            const uint64_t S = std::max<uint64_t>(1, full / d);
+            const int ks[] = {per_chunk, std::max(1, per_chunk / 2), 3, 2};
+            for (int k : ks) {
+                omc_params q = p;
+                q.chunk_histories = int(S);
+                q.graph_depth = std::max(1, std::min(64, k));
+                bool dup = false;
+                for (const auto& o : cand)
+                    dup = dup || (o.chunk_histories == q.chunk_histories &&
+                                  o.graph_depth == q.graph_depth);
+                if (!dup) cand.push_back(q);
+            }
+        }
+        for (size_t i = 0; i < cand.size(); ++i) {
+            if (i > 0) {
+                rc = timed(cand[i], ms, L);
+                if (rc != OMC_OK) {
+                    last_rc = rc;
+                    continue;
+                }
+            }
+            const uint64_t S = uint64_t(cand[i].chunk_histories);
+            if (double(L.queue_hwm_ph + L.queue_hwm_el) / double(S) >
+                double(hwm) / double(hwm_chunk)) {
+                hwm = L.queue_hwm_ph + L.queue_hwm_el;
+                hwm_chunk = S;
+            }
+            if (ms < top_ms) {
+                top_ms = ms;
+                top = cand[i];
+            }
+        }
+    }
+    drop_graph(c);
+    if (top_ms >= 1e300) {
+        c->prm = base;
+        return last_rc != OMC_OK ? last_rc : fail(c, OMC_EDEVICE, "no candidate completed");
+    }
+    // queue capacity: the largest occupancy per chunk history seen, with margin
+    const double per_hist = double(hwm) / double(hwm_chunk);
+    top.queue_factor = int(std::min(64.0, std::max(2.0, std::ceil(1.5 * per_hist + 1.0))));
+    top.timing = base.timing;
+    c->prm = top;
+    if (best) *best = top;
+    return OMC_OK;
 }
 
 int omc_get_counters(const omc_ctx* c, omc_counters* out)
@@ -878,9 +1573,13 @@ void omc_destroy(omc_ctx* c)
     free_tables(c->t64);
     free_queues(c->q32);
     free_queues(c->q64);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     dfree(c->d_rho);
     dfree(c->d_mat);
-    dfree(c->d_cdf);
+    dfree(c->d_src);
+    dfree(c->d_run);
+    dfree(c->d_cscratch);
     dfree(c->d_grid);
     dfree(c->d_dose);
     dfree(c->d_dose2);
@@ -888,6 +1587,7 @@ void omc_destroy(omc_ctx* c)
     dfree(c->d_counters);
     dfree(c->d_energies);
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+    if (c->h_run) (void)hipHostFree(c->h_run);
     delete c;
 }
 

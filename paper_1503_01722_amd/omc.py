@@ -20,7 +20,8 @@ NA = 512
 TABLE_ROWS = ["muC", "muPE", "muPair", "muTot", "Scol", "Srad", "R", "sigM", "sigB", "sigHat",
               "K1"]
 EXPORTS = ["omc_default_params", "omc_create", "omc_set_source", "omc_set_params", "omc_run",
-           "omc_run_device", "omc_get_counters", "omc_get_timing", "omc_debug_philox", "omc_debug_trace",
+           "omc_run_device", "omc_run_beamlets", "omc_free_sparse", "omc_autotune",
+           "omc_get_counters", "omc_get_timing", "omc_debug_philox", "omc_debug_trace",
            "omc_host_tables", "omc_host_ms_table", "omc_last_error", "omc_destroy"]
 
 
@@ -50,7 +51,22 @@ class Params(C.Structure):
                 ("kc", C.c_double), ("dmax_s", C.c_double), ("f_E", C.c_double),
                 ("n_batches", C.c_int), ("parity_fp64", C.c_int), ("kerma_mode", C.c_int),
                 ("csda_mode", C.c_int), ("block_size", C.c_int), ("blocks_per_cu", C.c_int),
-                ("chunk_histories", C.c_int), ("queue_factor", C.c_int), ("timing", C.c_int)]
+                ("chunk_histories", C.c_int), ("queue_factor", C.c_int), ("timing", C.c_int),
+                ("graph_depth", C.c_int), ("beamlet_group", C.c_int),
+                ("sparse_threshold", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Beamlet(C.Structure):
+    _fields_ = [("src", Source), ("n_histories", C.c_uint64), ("h0", C.c_uint32)]
+
+
+class SparseOut(C.Structure):
+    _fields_ = [("n_beamlets", C.c_int), ("on_device", C.c_int), ("nnz", C.c_uint64),
+                ("row_ptr", C.POINTER(C.c_uint64)), ("voxel", C.POINTER(C.c_uint32)),
+                ("dose", C.POINTER(C.c_float))]
 
 
 COUNTER_INT = ["ph_flights", "ph_fictitious", "ph_compton", "ph_photo", "ph_pair", "ph_cutoff",
@@ -109,6 +125,11 @@ def lib():
         L.omc_set_params.argtypes = [vp, C.POINTER(Params)]
         L.omc_run.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, dp, dp]
         L.omc_run_device.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp]
+        L.omc_run_beamlets.argtypes = [vp, C.POINTER(Beamlet), C.c_int, C.c_uint32, C.c_int, vp,
+                                       C.POINTER(SparseOut)]
+        L.omc_free_sparse.argtypes = [C.POINTER(SparseOut)]
+        L.omc_free_sparse.restype = None
+        L.omc_autotune.argtypes = [vp, C.c_uint64, C.c_uint32, C.POINTER(Params)]
         L.omc_get_counters.argtypes = [vp, C.POINTER(Counters)]
         L.omc_get_timing.argtypes = [vp, C.POINTER(Timing)]
         L.omc_debug_philox.argtypes = [C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -122,7 +143,8 @@ def lib():
         L.omc_destroy.argtypes = [vp]
         L.omc_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("omc_default_params", "omc_last_error", "omc_destroy"):
+            if name not in ("omc_default_params", "omc_last_error", "omc_destroy",
+                            "omc_free_sparse"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -185,17 +207,9 @@ class Engine:
             pass
 
     def set_source(self, src):
-        nb = int(src.get("n_bins", 0) or 0)
-        edges = np.ascontiguousarray(src.get("edges", np.zeros(1)), dtype=np.float64)
-        weights = np.ascontiguousarray(src.get("weights", np.zeros(1)), dtype=np.float64)
-        s = Source(int(src["particle"]), nb, _dptr(edges), _dptr(weights),
-                   float(src.get("mono_E", 0.0)), int(src["geometry"]),
-                   float(src.get("ssd", 100.0)), float(src.get("z_field", 0.0)),
-                   float(src["fx"]), float(src["fy"]), float(src["cx"]), float(src["cy"]),
-                   float(src.get("sx", src["cx"])), float(src.get("sy", src["cy"])),
-                   float(src.get("gantry_deg", 0.0)), float(src.get("iso_x", 0.0)),
-                   float(src.get("iso_z", 0.0)))
+        s, keep = _source_struct(src)
         _check(lib().omc_set_source(self._h, C.byref(s)), self._h)
+        del keep
 
     def set_params(self, **kw):
         p = Params.from_buffer_copy(self.params)
@@ -226,6 +240,33 @@ class Engine:
                                   C.c_void_p(dose2.data_ptr()), C.c_void_p(stream.cuda_stream))
         _check(rc, self._h)
 
+    def run_beamlets(self, beamlets, seed=1, on_device=False, stream=None):
+        """beamlets: list of (source dict, n_histories, h0). Returns a Sparse
+        holding the CSR rows (see omc_run_beamlets); host rows unless on_device."""
+        arr = (Beamlet * len(beamlets))()
+        keep, cache = [], {}
+        for i, (src, n, h0) in enumerate(beamlets):
+            s, k = _source_struct(src, cache)
+            keep.append(k)
+            arr[i] = Beamlet(s, int(n), int(h0))
+        out = SparseOut()
+        sp = None
+        if on_device:
+            import torch
+            sp = (stream or torch.cuda.current_stream()).cuda_stream
+        rc = lib().omc_run_beamlets(self._h, arr, len(beamlets), int(seed), int(bool(on_device)),
+                                    C.c_void_p(sp), C.byref(out))
+        _check(rc, self._h)
+        return Sparse(out)
+
+    def autotune(self, n_probe, seed=1):
+        """Pick the launch shape by timing (omc_autotune); returns the chosen
+        parameters as a dict and applies them."""
+        p = Params()
+        _check(lib().omc_autotune(self._h, int(n_probe), int(seed), C.byref(p)), self._h)
+        self.params = p
+        return p.as_dict()
+
     def trace(self, h, seed=1, max_records=1 << 16):
         """Step records of history h alone (see omc_debug_trace)."""
         out = np.zeros(max_records * 12)
@@ -243,6 +284,66 @@ class Engine:
         t = Timing()
         _check(lib().omc_get_timing(self._h, C.byref(t)), self._h)
         return t.as_dict()
+
+
+def _source_struct(src, cache=None):
+    """omc_source for a source dict, and the arrays it points into (keep them
+    alive during the call). Equal spectrum arrays share one buffer."""
+    nb = int(src.get("n_bins", 0) or 0)
+    key = (id(src.get("edges")), id(src.get("weights")), nb)
+    if cache is not None and key in cache:
+        edges, weights = cache[key]
+    else:
+        edges = np.ascontiguousarray(src.get("edges", np.zeros(1)), dtype=np.float64)
+        weights = np.ascontiguousarray(src.get("weights", np.zeros(1)), dtype=np.float64)
+        if cache is not None:
+            cache[key] = (edges, weights)
+    s = Source(int(src["particle"]), nb, _dptr(edges), _dptr(weights),
+               float(src.get("mono_E", 0.0)), int(src["geometry"]),
+               float(src.get("ssd", 100.0)), float(src.get("z_field", 0.0)),
+               float(src["fx"]), float(src["fy"]), float(src["cx"]), float(src["cy"]),
+               float(src.get("sx", src["cx"])), float(src.get("sy", src["cy"])),
+               float(src.get("gantry_deg", 0.0)), float(src.get("iso_x", 0.0)),
+               float(src.get("iso_z", 0.0)))
+    return s, (edges, weights)
+
+
+class Sparse:
+    """CSR rows of omc_run_beamlets; host rows are copied into numpy arrays."""
+
+    def __init__(self, out):
+        self._out = out
+        self.n_beamlets = out.n_beamlets
+        self.nnz = int(out.nnz)
+        self.on_device = bool(out.on_device)
+        self.row_ptr = (np.ctypeslib.as_array(out.row_ptr, (self.n_beamlets + 1,)).copy()
+                        if out.row_ptr else np.zeros(self.n_beamlets + 1, np.uint64))
+        if not self.on_device and self.nnz:
+            self.voxel = np.ctypeslib.as_array(out.voxel, (self.nnz,)).copy()
+            self.dose = np.ctypeslib.as_array(out.dose, (self.nnz,)).copy()
+            self.free()
+        elif not self.on_device:
+            self.voxel = np.zeros(0, np.uint32)
+            self.dose = np.zeros(0, np.float32)
+            self.free()
+
+    def row(self, b, nvox):
+        """Dense dose of beamlet b (host rows only)."""
+        d = np.zeros(nvox, np.float64)
+        lo, hi = int(self.row_ptr[b]), int(self.row_ptr[b + 1])
+        d[self.voxel[lo:hi]] = self.dose[lo:hi]
+        return d
+
+    def free(self):
+        if self._out is not None:
+            lib().omc_free_sparse(C.byref(self._out))
+            self._out = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def debug_philox(seed, h, q, n0, nblocks):

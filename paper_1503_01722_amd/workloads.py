@@ -210,3 +210,21 @@ def beamlets(phantom, n_angles=8, grid=8, size=0.5, sad=100.0, count_range=(100_
                 out.append((src, int(counts[k])))
                 k += 1
     return out
+
+
+# Launch shape of the batched-beamlet workload (graph generations per source
+# chunk, histories per chunk), shared by its benchmark and full-size test.
+BEAMLET_GRAPH_DEPTH = 5
+BEAMLET_CHUNK = 1 << 24
+BEAMLET_BLOCKS_PER_CU = 8
+
+
+def beamlet_job(phantom, **kw):
+    """The batched workload as omc_run_beamlets takes it: (source, n, h0) with
+    consecutive history ranges, so that every history of the job has its own
+    stream."""
+    out, h0 = [], 0
+    for src, n in beamlets(phantom, **kw):
+        out.append((src, n, h0))
+        h0 += n
+    return out

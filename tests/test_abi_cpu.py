@@ -38,6 +38,9 @@ def test_default_params(omc):
     p = omc.default_params()
     assert (p.Eabs_e, p.Eabs_g, p.Wcc, p.kc, p.dmax_s, p.f_E) == (0.2, 0.05, 0.05, 0.2, 0.5, 0.25)
     assert p.n_batches == 10 and p.parity_fp64 == 0 and p.block_size == 256
+    # the fields after the launch shape (a layout mismatch would show here)
+    assert (p.graph_depth, p.beamlet_group, p.sparse_threshold) == (0, 0, 0.0)
+    assert (p.queue_factor, p.timing, p.chunk_histories) == (6, 0, 0)
 
 
 def _create(omc, dens, mat, mats, dims=(4, 4, 4), h=(0.5, 0.5, 0.5)):
@@ -88,6 +91,13 @@ def test_argument_validation(omc, W):
     assert L.omc_set_params(None, None) == omc.OMC_EINVAL
     assert L.omc_run(None, 10, 1, 0, None, None) == omc.OMC_EINVAL
     assert L.omc_get_counters(None, None) == omc.OMC_EINVAL
+    assert L.omc_autotune(None, 1000, 1, None) == omc.OMC_EINVAL
+    out = omc.SparseOut()
+    out.nnz = 7  # zeroed by the call before it checks anything else
+    assert L.omc_run_beamlets(None, None, 1, 1, 0, None, C.byref(out)) == omc.OMC_EINVAL
+    assert out.nnz == 0 and not out.row_ptr
+    L.omc_free_sparse(None)
+    L.omc_free_sparse(C.byref(out))
     L.omc_destroy(None)
     if not gpu_present():
         rc, ctx = _create(omc, good_d, good_m, mats)
