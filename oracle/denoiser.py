@@ -172,23 +172,30 @@ def normalise(dose, sigma, rho, dmax):
     return np.stack([dose / dmax, sigma / dmax, rho / 2.0], axis=-1)
 
 
-def forward(theta, x):
+def _identity(v):
+    return v
+
+
+def forward(theta, x, store=_identity):
     """x: [Z, Y, X, 3] normalised input (Z, Y, X multiples of 8). Returns y =
-    x0 + delta and the activations the backward pass needs."""
+    x0 + delta and the activations the backward pass needs. `store` is applied
+    to every hidden activation as it is kept (identity: plain FP64; a rounding
+    function reproduces an implementation that stores activations in a
+    narrower format)."""
     P = unflatten(theta)
     a = {"x": x}
 
     def c3(name, inp):
         w, b = P[name]
-        return relu(conv3d(inp, w, b, 1, 1))
+        return store(relu(conv3d(inp, w, b, 1, 1)))
 
     def down(name, inp):
         w, b = P[name]
-        return relu(conv3d(inp, w, b, 2, 0))
+        return store(relu(conv3d(inp, w, b, 2, 0)))
 
     def up(name, inp):
         w, b = P[name]
-        return relu(conv_transpose2(inp, w, b))
+        return store(relu(conv_transpose2(inp, w, b)))
 
     a["enc1a"] = c3("enc1a", x)
     a["enc1b"] = c3("enc1b", a["enc1a"])
@@ -221,14 +228,15 @@ def loss(y, t):
     return float((w * r * r).sum() / W), 2.0 * w * r / W
 
 
-def backward(theta, a, gy):
+def backward(theta, a, gy, store=_identity):
     """Gradient of a scalar with respect to theta, given its gradient gy with
-    respect to the output y (chain rule through every layer, in reverse)."""
+    respect to the output y (chain rule through every layer, in reverse).
+    `store` is applied to every gradient after its ReLU mask (see forward)."""
     P = unflatten(theta)
     G = {}
 
     def relu_mask(g, out):
-        return g * (out > 0)
+        return store(g * (out > 0))
 
     wh, bh = P["head"]
     gdelta = gy[..., None]

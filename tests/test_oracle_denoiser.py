@@ -172,3 +172,21 @@ def test_adam_first_steps():
     for s in range(2, 6):
         th, m, v = dn.adam_step(th, g, m, v, s, 0.01, eps=0.0)
     np.testing.assert_allclose(th, -0.05 * np.sign(g), rtol=1e-10)
+
+
+def test_store_hook_defaults_to_plain_fp64():
+    """The optional storage-rounding hook is the identity unless given: a
+    rounding that does nothing leaves forward and backward bit-identical."""
+    rng = np.random.default_rng(8)
+    theta = dn.init_params(seed=2)
+    x = rng.random((8, 8, 8, 3))
+    y0, a0 = dn.forward(theta, x)
+    y1, a1 = dn.forward(theta, x, store=lambda v: v + 0.0)
+    assert np.array_equal(y0, y1)
+    t = x[..., 0] * 0.9
+    g0 = dn.backward(theta, a0, dn.loss(y0, t)[1])
+    g1 = dn.backward(theta, a1, dn.loss(y1, t)[1], store=lambda v: v * 1.0)
+    assert np.array_equal(g0, g1)
+    # a coarse rounding changes both (the hook is applied)
+    y2, _ = dn.forward(theta, x, store=lambda v: np.round(v, 1))
+    assert not np.array_equal(y0, y2)
