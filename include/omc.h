@@ -151,6 +151,9 @@ int omc_set_source(omc_ctx* ctx, const omc_source* src);
 /* Set parameters (copied). Rebuilds the electron tables when Wcc or kc change. */
 int omc_set_params(omc_ctx* ctx, const omc_params* p);
 
+/* The context's current parameters (after omc_autotune, the tuned ones). */
+int omc_get_params(const omc_ctx* ctx, omc_params* out);
+
 /* Transport histories h0 .. h0+n-1 with streams keyed by (seed, h) and write
  * dose (MeV/g per history) and dose2 = sum over batches of the squared batch
  * dose, both nx*ny*nz doubles in caller-owned host memory. h0 + n <= 2^32.

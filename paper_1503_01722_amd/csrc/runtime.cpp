@@ -1259,6 +1259,13 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
     return OMC_OK;
 }
 
+int omc_get_params(const omc_ctx* c, omc_params* out)
+{
+    if (!c || !out) return fail(nullptr, OMC_EINVAL, "NULL argument");
+    *out = c->prm;
+    return OMC_OK;
+}
+
 int omc_run_device(omc_ctx* c, uint64_t n, uint32_t seed, uint32_t h0, double* d_dose,
                    double* d_dose2, void* hip_stream)
 {

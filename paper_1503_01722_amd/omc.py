@@ -19,10 +19,17 @@ NE = 512
 NA = 512
 TABLE_ROWS = ["muC", "muPE", "muPair", "muTot", "Scol", "Srad", "R", "sigM", "sigB", "sigHat",
               "K1"]
-EXPORTS = ["omc_default_params", "omc_create", "omc_set_source", "omc_set_params", "omc_run",
-           "omc_run_device", "omc_run_beamlets", "omc_free_sparse", "omc_autotune",
-           "omc_get_counters", "omc_get_timing", "omc_debug_philox", "omc_debug_trace",
-           "omc_host_tables", "omc_host_ms_table", "omc_last_error", "omc_destroy"]
+EXPORTS = ["omc_default_params", "omc_create", "omc_set_source", "omc_set_params",
+           "omc_get_params", "omc_run", "omc_run_device", "omc_run_beamlets", "omc_free_sparse",
+           "omc_autotune", "omc_get_counters", "omc_get_timing", "omc_debug_philox",
+           "omc_debug_trace", "omc_host_tables", "omc_host_ms_table", "omc_last_error",
+           "omc_destroy",
+           # include/omc_dn.h
+           "omc_dn_create", "omc_dn_num_params", "omc_dn_get_params", "omc_dn_set_params",
+           "omc_dn_forward", "omc_dn_train_step", "omc_dn_gradient", "omc_dn_denoise",
+           "omc_dn_debug_layer", "omc_dn_last_error", "omc_dn_destroy"]
+VOID_FNS = ("omc_default_params", "omc_last_error", "omc_destroy", "omc_free_sparse",
+            "omc_dn_last_error", "omc_dn_destroy")
 
 
 class OmcError(RuntimeError):
@@ -123,6 +130,7 @@ def lib():
                                  C.POINTER(Material), C.c_int]
         L.omc_set_source.argtypes = [vp, C.POINTER(Source)]
         L.omc_set_params.argtypes = [vp, C.POINTER(Params)]
+        L.omc_get_params.argtypes = [vp, C.POINTER(Params)]
         L.omc_run.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, dp, dp]
         L.omc_run_device.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp]
         L.omc_run_beamlets.argtypes = [vp, C.POINTER(Beamlet), C.c_int, C.c_uint32, C.c_int, vp,
@@ -142,9 +150,23 @@ def lib():
         L.omc_last_error.restype = C.c_char_p
         L.omc_destroy.argtypes = [vp]
         L.omc_destroy.restype = None
+        fp = C.POINTER(C.c_float)
+        L.omc_dn_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.c_uint32]
+        L.omc_dn_num_params.argtypes = [vp, C.POINTER(C.c_uint64)]
+        L.omc_dn_get_params.argtypes = [vp, fp, C.c_uint64]
+        L.omc_dn_set_params.argtypes = [vp, fp, C.c_uint64]
+        L.omc_dn_forward.argtypes = [vp, vp, vp, vp, C.c_double, vp, vp]
+        L.omc_dn_train_step.argtypes = [vp, vp, vp, vp, C.c_double, vp, C.c_double, fp, vp]
+        L.omc_dn_gradient.argtypes = [vp, vp, vp, vp, C.c_double, vp, fp, C.c_uint64, fp, vp]
+        L.omc_dn_denoise.argtypes = [vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, C.c_double,
+                                     C.c_uint64, vp, dp, C.POINTER(C.c_int), vp]
+        L.omc_dn_debug_layer.argtypes = [C.c_int] * 7 + [fp] * 8
+        L.omc_dn_last_error.argtypes = [vp]
+        L.omc_dn_last_error.restype = C.c_char_p
+        L.omc_dn_destroy.argtypes = [vp]
+        L.omc_dn_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("omc_default_params", "omc_last_error", "omc_destroy",
-                            "omc_free_sparse"):
+            if name not in VOID_FNS:
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -275,6 +297,11 @@ class Engine:
                                      C.byref(n)), self._h)
         return out[: n.value * 12].reshape(n.value, 12)
 
+    def get_params(self):
+        p = Params()
+        _check(lib().omc_get_params(self._h, C.byref(p)), self._h)
+        return p.as_dict()
+
     def counters(self):
         c = Counters()
         _check(lib().omc_get_counters(self._h, C.byref(c)), self._h)
@@ -365,3 +392,128 @@ def host_ms_table():
     out = np.zeros(NA)
     _check(lib().omc_host_ms_table(_dptr(out)))
     return out
+
+
+# ------------------------------------------------------------------ denoiser
+def _dn_check(rc, h=None):
+    if rc != OMC_OK:
+        msg = lib().omc_dn_last_error(h)
+        raise OmcError(rc, msg.decode() if msg else "")
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
+
+
+def _dev(t, n=None):
+    """Device pointer of a contiguous float32 CUDA tensor (checked)."""
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    if n is not None:
+        assert t.numel() == n
+    return C.c_void_p(t.data_ptr())
+
+
+class Denoiser:
+    """The learned denoiser of include/omc_dn.h for volumes of `shape` (z, y, x)."""
+
+    def __init__(self, shape, seed=0):
+        self.shape = tuple(int(k) for k in shape)
+        nz, ny, nx = self.shape
+        h = C.c_void_p()
+        _dn_check(lib().omc_dn_create(C.byref(h), nx, ny, nz, int(seed)))
+        self._h = h
+        n = C.c_uint64()
+        _dn_check(lib().omc_dn_num_params(self._h, C.byref(n)), self._h)
+        self.n_params = n.value
+        self.nvox = nz * ny * nx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().omc_dn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.zeros(self.n_params, np.float32)
+        _dn_check(lib().omc_dn_get_params(self._h, _fptr(out), self.n_params), self._h)
+        return out
+
+    def set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        _dn_check(lib().omc_dn_set_params(self._h, _fptr(t), t.size), self._h)
+
+    def _stream(self, stream):
+        import torch
+        return C.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+    def forward(self, dose, sigma, rho, dmax, out, stream=None):
+        _dn_check(lib().omc_dn_forward(self._h, _dev(dose, self.nvox), _dev(sigma, self.nvox),
+                                       _dev(rho, self.nvox), float(dmax), _dev(out, self.nvox),
+                                       self._stream(stream)), self._h)
+
+    def train_step(self, dose, sigma, rho, dmax, target, lr, stream=None):
+        loss = C.c_float()
+        _dn_check(lib().omc_dn_train_step(self._h, _dev(dose, self.nvox), _dev(sigma, self.nvox),
+                                          _dev(rho, self.nvox), float(dmax),
+                                          _dev(target, self.nvox), float(lr), C.byref(loss),
+                                          self._stream(stream)), self._h)
+        return loss.value
+
+    def gradient(self, dose, sigma, rho, dmax, target, stream=None):
+        g = np.zeros(self.n_params, np.float32)
+        loss = C.c_float()
+        _dn_check(lib().omc_dn_gradient(self._h, _dev(dose, self.nvox), _dev(sigma, self.nvox),
+                                        _dev(rho, self.nvox), float(dmax),
+                                        _dev(target, self.nvox), _fptr(g), self.n_params,
+                                        C.byref(loss), self._stream(stream)), self._h)
+        return g, loss.value
+
+    def denoise(self, engine, n_low, seed, h0, rho, max_err, n_fallback, out, stream=None):
+        err = C.c_double()
+        fb = C.c_int()
+        _dn_check(lib().omc_dn_denoise(self._h, engine._h, int(n_low), int(seed), int(h0),
+                                       _dev(rho, self.nvox), float(max_err), int(n_fallback),
+                                       _dev(out, self.nvox), C.byref(err), C.byref(fb),
+                                       self._stream(stream)), self._h)
+        return err.value, bool(fb.value)
+
+
+def dn_debug_layer(geometry, x, w, b, gy, c0, c1, want=("y", "gx", "gw", "gb")):
+    """One layer on the GPU (omc_dn_debug_layer). x: [z, y, x, c0 + c1], w:
+    [taps, c0 + c1, cout] float32; gy: output gradient [z', y', x', cout]."""
+    x = np.ascontiguousarray(x, np.float32)
+    w = np.ascontiguousarray(w, np.float32)
+    nz, ny, nx, cin = x.shape
+    cout = w.shape[-1]
+    if geometry == 0:
+        oshape = (nz, ny, nx)
+    elif geometry == 1:
+        oshape = (nz // 2, ny // 2, nx // 2)
+    else:
+        oshape = (2 * nz, 2 * ny, 2 * nx)
+    no = int(np.prod(oshape))
+    b = np.ascontiguousarray(b, np.float32)
+    gy = np.ascontiguousarray(gy, np.float32) if gy is not None else None
+    y = np.zeros(no * cout, np.float32) if "y" in want else None
+    gx = np.zeros(x.size, np.float32) if "gx" in want else None
+    gw = np.zeros(w.size, np.float32) if "gw" in want else None
+    gb = np.zeros(cout, np.float32) if "gb" in want else None
+    rc = lib().omc_dn_debug_layer(geometry, nx, ny, nz, c0, c1, cout, _fptr(x), _fptr(w), _fptr(b),
+                                  _fptr(gy), _fptr(y), _fptr(gx), _fptr(gw), _fptr(gb))
+    _dn_check(rc)
+    res = {}
+    if y is not None:
+        res["y"] = y.reshape(oshape + (cout,))
+    if gx is not None:
+        res["gx"] = gx.reshape(x.shape)
+    if gw is not None:
+        res["gw"] = gw.reshape(w.shape)
+    if gb is not None:
+        res["gb"] = gb
+    return res

@@ -107,27 +107,84 @@ def halfslab_phantom(n=256, h=0.2, x_split=None):
     return _phantom(d, m, (h, h, h))
 
 
-def ellipsoid_phantom(shape=(160, 256, 256), h=0.2, n_ell=12, seed=1):
-    """CT-like phantom: water background and n_ell seeded ellipsoids (centres in
-    the inner 80 %, semi-axes U[1,6] cm, random rotation, density U[0.2,1.9]),
-    painted in order; material by density thresholds."""
+def ellipsoid_params(shape, h, n_ell, seed):
+    """Seeded ellipsoids of the CT-like phantom, in painting order: centre
+    (x, y, z) uniform in the inner 80 %, semi-axes U[1, 6] cm, a random
+    rotation (QR of a normal matrix), density U[0.2, 1.9]."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = shape
     L = np.array([nx * h, ny * h, nz * h])
-    d = np.ones(shape, dtype=np.float32)
-    zc = (np.arange(nz) + 0.5) * h
-    yc = (np.arange(ny) + 0.5) * h
-    xc = (np.arange(nx) + 0.5) * h
-    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    out = []
     for _ in range(n_ell):
         c = L * (0.1 + 0.8 * rng.random(3))
         ax = rng.uniform(1.0, 6.0, 3)
         q, _r = np.linalg.qr(rng.normal(size=(3, 3)))
         rho = rng.uniform(0.2, 1.9)
+        out.append((c, ax, q, rho))
+    return out
+
+
+def ellipsoid_phantom(shape=(160, 256, 256), h=0.2, n_ell=12, seed=1):
+    """CT-like phantom: water background and n_ell seeded ellipsoids (see
+    ellipsoid_params), painted in order; material by density thresholds."""
+    nz, ny, nx = shape
+    d = np.ones(shape, dtype=np.float32)
+    zc = (np.arange(nz) + 0.5) * h
+    yc = (np.arange(ny) + 0.5) * h
+    xc = (np.arange(nx) + 0.5) * h
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    for c, ax, q, rho in ellipsoid_params(shape, h, n_ell, seed):
         P = np.stack([X - c[0], Y - c[1], Z - c[2]], axis=-1) @ q
         inside = ((P / ax) ** 2).sum(-1) <= 1.0
         d[inside] = rho
     return _phantom(d, material_from_density(d), (h, h, h))
+
+
+def ellipsoid_phantom_gpu(shape=(128, 128, 128), h=0.25, n_ell=12, seed=1):
+    """The same phantom as ellipsoid_phantom, painted on the GPU with torch
+    (fast enough to make thousands of them); returned as host arrays."""
+    import torch
+    nz, ny, nx = shape
+    dev = "cuda"
+    zc = (torch.arange(nz, device=dev, dtype=torch.float64) + 0.5) * h
+    yc = (torch.arange(ny, device=dev, dtype=torch.float64) + 0.5) * h
+    xc = (torch.arange(nx, device=dev, dtype=torch.float64) + 0.5) * h
+    Z, Y, X = torch.meshgrid(zc, yc, xc, indexing="ij")
+    d = torch.ones(shape, device=dev, dtype=torch.float32)
+    for c, ax, q, rho in ellipsoid_params(shape, h, n_ell, seed):
+        qt = torch.tensor(q, device=dev)
+        px, py, pz = X - float(c[0]), Y - float(c[1]), Z - float(c[2])
+        s = 0.0
+        for k in range(3):
+            comp = px * qt[0, k] + py * qt[1, k] + pz * qt[2, k]
+            s = s + (comp / float(ax[k])) ** 2
+        d[s <= 1.0] = float(rho)
+    dn = d.cpu().numpy()
+    return _phantom(dn, material_from_density(dn), (h, h, h))
+
+
+def denoiser_pair(i, shape=(128, 128, 128), h=0.25):
+    """Pair i of the denoiser's training set: phantom as the CT-like one with
+    seed 1000 + i; beam from default_rng(5000 + i): 6 MV or 15 MeV electrons
+    (p = 1/2), square field U[2, 10] cm on the isocentre plane, centre offset
+    U[-3, 3] cm in x and y, gantry in {0, 90, 180, 270} about y through the
+    phantom centre, point source 100 cm from the isocentre. Low / high runs
+    use seeds 2i + 1 / 2i + 2. Returns (phantom seed, source, seeds)."""
+    rng = np.random.default_rng(5000 + i)
+    nz, ny, nx = shape
+    iso = np.array([nx * h / 2.0, ny * h / 2.0, nz * h / 2.0])
+    photon = bool(rng.random() < 0.5)
+    f = float(rng.uniform(2.0, 10.0))
+    off = rng.uniform(-3.0, 3.0, 2)
+    g = float(rng.choice([0.0, 90.0, 180.0, 270.0]))
+    cx, cy = float(iso[0] + off[0]), float(iso[1] + off[1])
+    if photon:
+        src = photon_beam((f, f), (cx, cy), spectrum=spectrum_6mv(), ssd=100.0)
+    else:
+        src = electron_beam(15.0, (f, f), (cx, cy), parallel=False, ssd=100.0)
+    src.update(z_field=float(iso[2]), sx=float(iso[0]), sy=float(iso[1]), gantry_deg=g,
+               iso_x=float(iso[0]), iso_z=float(iso[2]))
+    return 1000 + i, src, (2 * i + 1, 2 * i + 2)
 
 
 def spectrum_6mv(n_bins=64, e_lo=0.2, e_hi=6.0, seed=1):

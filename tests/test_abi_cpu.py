@@ -20,14 +20,17 @@ def omc():
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "omc.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(omc_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in ("omc.h", "omc_dn.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(omc_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(omc):
     names = header_functions()
-    assert len(names) >= 13
+    assert len(names) >= 28
     L = omc.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -99,6 +102,15 @@ def test_argument_validation(omc, W):
     L.omc_free_sparse(None)
     L.omc_free_sparse(C.byref(out))
     L.omc_destroy(None)
+    # denoiser: invalid volume sides are rejected before any device call
+    h = C.c_void_p()
+    for dims in ((12, 16, 16), (16, 16, 4), (1024, 16, 16)):
+        assert L.omc_dn_create(C.byref(h), *dims, 0) == omc.OMC_EINVAL and not h.value
+    assert L.omc_dn_num_params(None, None) == omc.OMC_EINVAL
+    assert L.omc_dn_forward(None, None, None, None, 1.0, None, None) == omc.OMC_EINVAL
+    assert L.omc_dn_debug_layer(5, 8, 8, 8, 16, 0, 16, *([None] * 8)) == omc.OMC_EINVAL
+    assert L.omc_dn_last_error(None)
+    L.omc_dn_destroy(None)
     if not gpu_present():
         rc, ctx = _create(omc, good_d, good_m, mats)
         assert rc == omc.OMC_EDEVICE and not ctx.value

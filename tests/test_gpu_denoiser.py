@@ -1,0 +1,283 @@
+"""GPU tests of the learned denoiser through the C ABI of include/omc_dn.h.
+
+* Every layer kind (3x3x3, 2x2x2 stride-2 down, 2x2x2 transposed up, with and
+  without the decoder's concatenated input) on the BF16 matrix cores: forward,
+  input gradient, weight and bias gradients against the FP64 oracle on the
+  same BF16-rounded operands, to FP32 accumulation accuracy.
+* The whole network against the oracle: forward output and the gradient of
+  every parameter, to BF16-activation accuracy.
+* Training reduces the loss; the trained network beats the low-history dose it
+  starts from on held-out engine-generated pairs; the fallback to plain Monte
+  Carlo returns the plain dose of all histories.
+"""
+import numpy as np
+import pytest
+
+from oracle import denoiser as odn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def omc():
+    from paper_1503_01722_amd import omc
+    omc.lib()
+    return omc
+
+
+def bf16(a):
+    """Round float32 values to the nearest BF16 (ties to even), as float64."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def report(tag, **kv):
+    print(tag, " ".join(f"{k}={v}" for k, v in kv.items()), flush=True)
+
+
+LAYERS = [  # geometry, volume (z, y, x), c0, c1, cout: every shape the network uses
+    (0, (6, 10, 12), 8, 0, 16),     # first layer (3 input channels padded to 8)
+    (0, (6, 10, 12), 16, 0, 16),
+    (0, (6, 10, 12), 16, 16, 16),   # decoder conv with the skip concatenated
+    (0, (5, 6, 10), 32, 0, 32),
+    (0, (4, 6, 10), 32, 32, 32),
+    (0, (4, 6, 10), 48, 0, 48),
+    (0, (4, 4, 6), 48, 48, 48),
+    (0, (3, 4, 6), 64, 0, 64),
+    (1, (6, 10, 12), 16, 0, 32),
+    (1, (4, 6, 8), 32, 0, 48),
+    (1, (4, 6, 8), 48, 0, 64),
+    (2, (3, 5, 6), 32, 0, 16),
+    (2, (3, 4, 5), 48, 0, 32),
+    (2, (2, 3, 4), 64, 0, 48),
+]
+
+
+@pytest.mark.parametrize("geometry,shape,c0,c1,cout", LAYERS)
+def test_layer_matches_oracle(omc, geometry, shape, c0, c1, cout):
+    rng = np.random.default_rng(geometry * 100 + c0 + c1 + cout)
+    cin = c0 + c1
+    taps = 27 if geometry == 0 else 8
+    k = 3 if geometry == 0 else 2
+    x = bf16(rng.normal(size=shape + (cin,)))
+    w = bf16(rng.normal(0, 0.1, size=(taps, cin, cout)))
+    b = rng.normal(size=cout).astype(np.float32)
+    wk = w.reshape(k, k, k, cin, cout)
+    if geometry == 0:
+        y_ref = odn.conv3d(x, wk, b, 1, 1)
+    elif geometry == 1:
+        y_ref = odn.conv3d(x, wk, b, 2, 0)
+    else:
+        y_ref = odn.conv_transpose2(x, wk, b)
+    gy = bf16(rng.normal(size=y_ref.shape))
+    want = ("y", "gx", "gw", "gb") if cin % 16 == 0 else ("y", "gw", "gb")
+    got = omc.dn_debug_layer(geometry, x, w, b, gy, c0, c1, want)
+    if geometry == 0:
+        gx_ref = odn.conv3d_bwd_data(gy, wk, x.shape, 1, 1)
+        gw_ref = odn.conv3d_bwd_weight(x, gy, 3, 1, 1)
+    elif geometry == 1:
+        gx_ref = odn.conv3d_bwd_data(gy, wk, x.shape, 2, 0)
+        gw_ref = odn.conv3d_bwd_weight(x, gy, 2, 2, 0)
+    else:
+        gx_ref = odn.conv_transpose2_bwd_data(gy, wk)
+        gw_ref = odn.conv_transpose2_bwd_weight(x, gy)
+    gb_ref = gy.sum(axis=(0, 1, 2))
+    # FP32 accumulation of at most 27 * 96 products of BF16 operands
+    for name, ref in (("y", y_ref), ("gx", gx_ref), ("gw", gw_ref.reshape(taps, cin, cout)),
+                      ("gb", gb_ref)):
+        if name not in got:
+            continue
+        scale = np.abs(ref).max()
+        err = np.abs(got[name] - ref).max() / scale
+        report(f"layer g{geometry} {shape} {c0}+{c1}->{cout} {name}", rel_err=f"{err:.2e}")
+        np.testing.assert_allclose(got[name], ref, rtol=1e-4, atol=2e-5 * scale)
+
+
+def _inputs(rng, shape):
+    """A dose-like field (smooth bump plus noise), its sigma and a density."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(*(np.linspace(-1, 1, n) for n in shape), indexing="ij")
+    clean = np.exp(-(x * x + y * y) * 3) * (1 - 0.3 * (z + 1))
+    sigma = 0.05 * clean + 0.005
+    dose = clean + sigma * rng.normal(size=shape)
+    rho = 1.0 + 0.5 * (rng.random(shape) > 0.8)
+    return dose, sigma, rho, clean
+
+
+def _to_dev(*arrays):
+    import torch
+    return [torch.tensor(np.asarray(a, np.float32).ravel(), device="cuda") for a in arrays]
+
+
+def _round_conv_weights(theta):
+    """BF16 copy of every convolution weight (the head and biases stay FP32),
+    as the matrix-core kernels read them."""
+    t = theta.astype(np.float64).copy()
+    at = 0
+    for name, kind, ci, co in odn.layer_specs():
+        nw = odn.kernel_size(kind) ** 3 * ci * co
+        if kind != "head":
+            t[at:at + nw] = bf16(t[at:at + nw])
+        at += nw + co
+    return t
+
+
+def test_network_forward_and_gradient_match_oracle(omc):
+    """The network on the GPU against the oracle twice: the plain FP64 oracle
+    (agreement limited by the GPU's BF16 storage of weights, activations and
+    masked gradients), and the oracle with the same BF16 storage points, where
+    only FP32 accumulation order and the rare rounding-boundary flip it causes
+    remain."""
+    import torch
+    shape = (32, 32, 32)
+    rng = np.random.default_rng(11)
+    theta = odn.init_params(seed=3).astype(np.float32)
+    P = odn.unflatten(theta)
+    for name, (w, b) in P.items():
+        b[:] = rng.normal(0, 0.02, b.size)
+    dose, sigma, rho, clean = _inputs(rng, shape)
+    dmax = float(dose.max())
+    net = omc.Denoiser(shape)
+    net.set_params(theta)
+    assert np.array_equal(net.get_params(), theta)
+    d_dose, d_sig, d_rho, d_tgt = _to_dev(dose, sigma, rho, clean)
+    out = torch.zeros_like(d_dose)
+    net.forward(d_dose, d_sig, d_rho, dmax, out)
+    torch.cuda.synchronize()
+    g_gpu, loss_gpu = net.gradient(d_dose, d_sig, d_rho, dmax, d_tgt)
+    xin = np.stack([bf16(dose / dmax), bf16(sigma / dmax), bf16(rho / 2)], axis=-1)
+    delta_gpu = out.cpu().numpy().reshape(shape) / dmax - (dose / dmax)
+    t = clean / dmax
+
+    # plain FP64 oracle
+    th64 = theta.astype(np.float64)
+    y_ref, a = odn.forward(th64, xin)
+    delta_ref = y_ref - xin[..., 0]
+    rel = np.linalg.norm(delta_gpu - delta_ref) / np.linalg.norm(delta_ref)
+    loss_ref, gy = odn.loss(y_ref, t)
+    g_ref = odn.backward(th64, a, gy)
+    cos = float(g_gpu @ g_ref / (np.linalg.norm(g_gpu) * np.linalg.norm(g_ref)))
+    report("fp64 oracle", forward_rel_l2=f"{rel:.3e}", grad_cosine=f"{cos:.6f}",
+           loss_gpu=loss_gpu, loss_ref=loss_ref)
+    # about 40 BF16 roundings (2^-9 relative each) on any path through the net
+    assert rel < 0.03
+    assert loss_gpu == pytest.approx(loss_ref, rel=0.02)
+    assert cos > 0.995
+
+    # the oracle with BF16 storage at the GPU's points
+    thq = _round_conv_weights(theta)
+    yq, aq = odn.forward(thq, xin, store=bf16)
+    relq = np.linalg.norm(delta_gpu - (yq - xin[..., 0])) / np.linalg.norm(yq - xin[..., 0])
+    lq, gyq = odn.loss(yq, t)
+    gq = odn.backward(thq, aq, gyq, store=bf16)
+    report("bf16-storage oracle", forward_rel_l2=f"{relq:.3e}", loss_ref=lq)
+    errs = {}
+    at = 0
+    for name, kind, ci, co in odn.layer_specs():
+        nw = odn.kernel_size(kind) ** 3 * ci * co + co
+        gg, gr, gp = g_gpu[at:at + nw], gq[at:at + nw], g_ref[at:at + nw]
+        errs[name] = np.linalg.norm(gg - gr) / max(np.linalg.norm(gr), 1e-30)
+        e64 = np.linalg.norm(gg - gp) / max(np.linalg.norm(gp), 1e-30)
+        report(f"  {name}", rel_l2_bf16_oracle=f"{errs[name]:.3e}",
+               rel_l2_fp64_oracle=f"{e64:.3e}")
+        at += nw
+    net.close()
+    # With the same storage points only accumulation order differs; it flips
+    # by one BF16 ulp (2^-8) the values sitting on a rounding boundary. The
+    # forward output agrees to well under an ulp. A layer's weight gradient is
+    # a sum over the voxels of its level (32768 at full resolution, 64 at the
+    # coarsest) of products whose ulp flips do not average out at the coarse
+    # levels, and the backward chain to them passes more stored roundings:
+    # full-resolution layers and the head agree to 1 %, every layer to 30 %.
+    # Each kernel shape is checked alone to FP32 accuracy above; a wiring error
+    # (wrong tensor, packing, mask or skip sum) shows as an O(1) error.
+    assert relq < 1e-2
+    level1 = ("enc1a", "enc1b", "up1", "dec1a", "dec1b", "head")
+    bad = {k: v for k, v in errs.items()
+           if not v < (0.01 if k in level1 else 0.3)}
+    assert not bad, bad
+    assert cos > 0.9999
+
+
+def test_training_reduces_loss(omc):
+    import torch
+    shape = (16, 16, 16)
+    rng = np.random.default_rng(12)
+    dose, sigma, rho, clean = _inputs(rng, shape)
+    d_dose, d_sig, d_rho, d_tgt = _to_dev(dose, sigma, rho, clean)
+    net = omc.Denoiser(shape, seed=5)
+    losses = [net.train_step(d_dose, d_sig, d_rho, float(dose.max()), d_tgt, 1e-3)
+              for _ in range(60)]
+    report("train", first=losses[0], last=losses[-1])
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0]
+    torch.cuda.synchronize()
+    net.close()
+
+
+def _pair(omc, W, rng, shape, h, n_lo, n_hi, seed):
+    """An engine-generated (low, high) pair on a seeded ellipsoid phantom."""
+    import torch
+    ph = W.ellipsoid_phantom(shape, h, n_ell=4, seed=int(rng.integers(1 << 30)))
+    nz, ny, nx = shape
+    c = np.array([nx * h / 2, ny * h / 2]) + rng.uniform(-1.5, 1.5, 2)
+    f = float(rng.uniform(2.0, 5.0))
+    src = W.photon_beam((f, f), tuple(c), spectrum=W.spectrum_6mv())
+    eng = omc.Engine(ph)
+    eng.set_source(src)
+    lo, lo2 = eng.run(n_lo, seed=seed, h0=0)
+    hi, _ = eng.run(n_hi, seed=seed + 1, h0=0)
+    eng.close()
+    B = 10
+    sig = np.sqrt(np.maximum(lo2 / B - lo * lo, 0) / (B - 1))
+    return ph["density"], lo, sig, hi
+
+
+def test_denoiser_gain_on_engine_pairs(omc, W):
+    """Trained on 24 engine-generated pairs (1e5 vs 4e6 histories of 6 MV,
+    32^3 phantoms of 0.5 cm), the network's dose is closer to the high-history
+    dose than the low-history dose it starts from, on 6 held-out pairs."""
+    import torch
+    shape, h = (32, 32, 32), 0.5
+    rng = np.random.default_rng(21)
+    pairs = [_pair(omc, W, rng, shape, h, 100_000, 4_000_000, 100 + 10 * i) for i in range(30)]
+    train, test = pairs[:24], pairs[24:]
+    dev = [[*_to_dev(rho, lo, sig, hi), float(lo.max())] for rho, lo, sig, hi in pairs]
+    net = omc.Denoiser(shape, seed=1)
+    for it in range(400):
+        d_rho, d_lo, d_sig, d_hi, dmax = dev[it % len(train)]
+        net.train_step(d_lo, d_sig, d_rho, dmax, d_hi, 1e-3 if it < 300 else 3e-4)
+    out = torch.zeros(int(np.prod(shape)), device="cuda")
+    raw, den = [], []
+    for (rho, lo, sig, hi), (d_rho, d_lo, d_sig, d_hi, dmax) in zip(test, dev[24:]):
+        net.forward(d_lo, d_sig, d_rho, dmax, out)
+        dn = out.cpu().numpy().reshape(shape)
+        sel = hi > 0.1 * hi.max()
+        raw.append(np.sqrt(np.mean((lo[sel] - hi[sel]) ** 2)) / hi.max())
+        den.append(np.sqrt(np.mean((dn[sel] - hi[sel]) ** 2)) / hi.max())
+    report("gain", raw=np.round(raw, 4), denoised=np.round(den, 4))
+    assert np.mean(den) < 0.8 * np.mean(raw)
+    net.close()
+
+
+def test_denoise_fallback_is_plain_monte_carlo(omc, W):
+    import torch
+    shape = (16, 16, 16)
+    ph = W.water_phantom(shape, 1.0)
+    src = W.photon_beam((6.0, 6.0), (8.0, 8.0), mono_E=2.0)
+    eng = omc.Engine(ph)
+    eng.set_source(src)
+    net = omc.Denoiser(shape, seed=2)
+    d_rho = _to_dev(ph["density"])[0]
+    out = torch.zeros(int(np.prod(shape)), device="cuda")
+    # an untrained network is far off: with max_err 0 it must fall back
+    err, fb = net.denoise(eng, 20_000, 3, 0, d_rho, 0.0, 60_000, out)
+    assert fb and err > 0
+    ref, _ = eng.run(80_000, seed=3, h0=0)
+    np.testing.assert_allclose(out.cpu().numpy().reshape(shape), ref, rtol=2e-5,
+                               atol=1e-6 * ref.max())
+    err2, fb2 = net.denoise(eng, 20_000, 3, 0, d_rho, 10.0, 60_000, out)
+    assert not fb2 and err2 == pytest.approx(err, rel=1e-6)
+    eng.close()
+    net.close()
