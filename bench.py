@@ -47,7 +47,35 @@ WORKLOADS = {
     "beamlets_c4": "512 beamlets 0.5x0.5 cm2 of 6 MV (8 gantry angles x 8x8), 1e5-1e6 histories "
                    "each (2.84e8 in all), 256x256x160 CT-like phantom of 0.2 cm voxels (12 "
                    "seeded ellipsoids, 0.2-1.9 g/cm3), per-beamlet sparse FP32 dose in HBM",
+    "denoiser_128": "learned denoiser (4-level U-Net, 16/32/48/64 channels, BF16 matrix cores) "
+                    "on 128^3 volumes: one training step (forward, backward, Adam) per step, "
+                    "plus the forward (inference) time",
 }
+
+# MI355X dense BF16 matrix-core peak (TFLOP/s)
+PEAK_BF16_TFLOPS = 2500.0
+
+
+# (level, taps, c_in, c_out, grid) per layer of the U-Net; grid is the level
+# whose voxels are the GEMM rows (the coarse input for the transposed up conv)
+DN_LAYERS = [(0, 27, 3, 16, 0), (0, 27, 16, 16, 0), (1, 8, 16, 32, 1), (1, 27, 32, 32, 1),
+             (1, 27, 32, 32, 1), (2, 8, 32, 48, 2), (2, 27, 48, 48, 2), (2, 27, 48, 48, 2),
+             (3, 8, 48, 64, 3), (3, 27, 64, 64, 3), (3, 27, 64, 64, 3), (2, 8, 64, 48, 3),
+             (2, 27, 96, 48, 2), (2, 27, 48, 48, 2), (1, 8, 48, 32, 2), (1, 27, 64, 32, 1),
+             (1, 27, 32, 32, 1), (0, 8, 32, 16, 1), (0, 27, 32, 16, 0), (0, 27, 16, 16, 0),
+             (0, 1, 16, 1, 0)]
+
+
+def denoiser_flops(n):
+    """Algorithmic FLOPs of the U-Net on a volume of n voxels: forward, and one
+    training step (forward + input gradients + weight gradients; the first
+    layer needs no input gradient). A multiply-add counts 2."""
+    fwd = bwd = 0.0
+    for k, (_, taps, ci, co, grid) in enumerate(DN_LAYERS):
+        f = 2.0 * (n / 8 ** grid) * taps * ci * co
+        fwd += f
+        bwd += f * (1 if k == 0 else 2)
+    return fwd, fwd + bwd
 
 # launch shape per workload: graph generations per source chunk, histories per
 # chunk (0 = 2^24), work-groups per CU (what omc_autotune picks on MI355X; the
@@ -116,6 +144,56 @@ def cpu_baseline_beamlets(ph, job, target_s, threads):
                       f"({n} in all, FP64 C oracle, OpenMP), {dt:.1f} s"}
 
 
+def bench_denoiser(args, omc, torch, np):
+    """Training steps and inference of the denoiser on 128^3 volumes of
+    synthetic dose-like inputs (a seeded smooth field plus noise)."""
+    n_side = 128
+    shape = (n_side,) * 3
+    nv = n_side ** 3
+    g = torch.Generator(device="cuda").manual_seed(1)
+    z, y, x = torch.meshgrid(*(torch.linspace(-1, 1, n_side, device="cuda"),) * 3, indexing="ij")
+    clean = (torch.exp(-(x * x + y * y) * 3) * (1 - 0.3 * (z + 1))).ravel().contiguous()
+    sigma = (0.05 * clean + 0.005).contiguous()
+    dose = (clean + sigma * torch.randn(nv, device="cuda", generator=g)).contiguous()
+    rho = (1.0 + 0.5 * (torch.rand(nv, device="cuda", generator=g) > 0.8).float()).contiguous()
+    out = torch.zeros(nv, device="cuda")
+    net = omc.Denoiser(shape, seed=7)
+    dmax = float(dose.max())
+    for _ in range(args.warmup):
+        net.train_step(dose, sigma, rho, dmax, clean, 1e-4)
+        net.forward(dose, sigma, rho, dmax, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(dose, sigma, rho, dmax, clean, 1e-4)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / args.steps
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.steps):
+        net.forward(dose, sigma, rho, dmax, out, stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_fwd = ev[0].elapsed_time(ev[1]) / 1e3 / args.steps
+    f_fwd, f_train = denoiser_flops(nv)
+    achieved = f_fwd / t_fwd / 1e12
+    res = {"metric": "training volumes/s", "value": 1.0 / t_train, "unit": "volumes/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * t_train, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "denoiser_128", "description": WORKLOADS["denoiser_128"],
+                      "volume": list(shape), "params": net.n_params},
+           "inference_ms": 1e3 * t_fwd,
+           "train_tflops": f_train / t_train / 1e12,
+           "roofline": {"bound": "mfma", "kernel": "forward pass (all layers)",
+                        "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                        "flops_per_forward": f_fwd}}
+    net.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +238,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "denoiser_128":
+        bench_denoiser(args, omc, torch, np)
+        return
     beamlets = args.workload == "beamlets_c4"
     if beamlets:
         ph = W.ellipsoid_phantom()

@@ -145,6 +145,12 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
                const float* density, const uint8_t* material, const omc_material* mats,
                int n_mats);
 
+/* Replace the phantom's densities and material ids (same dimensions, voxel
+ * sizes and materials; copied, validated as in omc_create). The physics
+ * tables of the materials are kept; the photon majorant, which depends on
+ * the largest density of each material, is rebuilt. */
+int omc_set_phantom(omc_ctx* ctx, const float* density, const uint8_t* material);
+
 /* Set the source (copied). Spectrum weights must have a positive sum. */
 int omc_set_source(omc_ctx* ctx, const omc_source* src);
 

@@ -1222,6 +1222,29 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
     return OMC_OK;
 }
 
+int omc_set_phantom(omc_ctx* c, const float* density, const uint8_t* material)
+{
+    if (check_ctx(c) || !density || !material) return fail(c, OMC_EINVAL, "NULL argument");
+    const int nm = int(c->mats.size());
+    std::vector<double> rmax(nm, 0.0);
+    for (size_t v = 0; v < c->nvox; ++v) {
+        const float r = density[v];
+        if (!(std::isfinite(r) && r > 0.0f) || material[v] >= nm)
+            return fail(c, OMC_EINVAL, "density must be finite and > 0 and material ids < n_mats");
+        rmax[material[v]] = std::max(rmax[material[v]], double(r));
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    c->rho.assign(density, density + c->nvox);
+    c->mat.assign(material, material + c->nvox);
+    c->rho_max = rmax;
+    HIP_TRY(c, hipMemcpy(c->d_rho, c->rho.data(), c->nvox * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_mat, c->mat.data(), c->nvox, hipMemcpyHostToDevice));
+    // the majorant depends on rho_max: rebuild the device tables on the next run
+    c->t32.valid = false;
+    c->t64.valid = false;
+    return OMC_OK;
+}
+
 int omc_set_source(omc_ctx* c, const omc_source* s)
 {
     if (check_ctx(c) || !s) return fail(c, OMC_EINVAL, "NULL argument");

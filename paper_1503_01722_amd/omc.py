@@ -19,7 +19,8 @@ NE = 512
 NA = 512
 TABLE_ROWS = ["muC", "muPE", "muPair", "muTot", "Scol", "Srad", "R", "sigM", "sigB", "sigHat",
               "K1"]
-EXPORTS = ["omc_default_params", "omc_create", "omc_set_source", "omc_set_params",
+EXPORTS = ["omc_default_params", "omc_create", "omc_set_phantom", "omc_set_source",
+           "omc_set_params",
            "omc_get_params", "omc_run", "omc_run_device", "omc_run_beamlets", "omc_free_sparse",
            "omc_autotune", "omc_get_counters", "omc_get_timing", "omc_debug_philox",
            "omc_debug_trace", "omc_host_tables", "omc_host_ms_table", "omc_last_error",
@@ -128,6 +129,7 @@ def lib():
         L.omc_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                  C.c_double, C.POINTER(C.c_float), C.POINTER(C.c_uint8),
                                  C.POINTER(Material), C.c_int]
+        L.omc_set_phantom.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint8)]
         L.omc_set_source.argtypes = [vp, C.POINTER(Source)]
         L.omc_set_params.argtypes = [vp, C.POINTER(Params)]
         L.omc_get_params.argtypes = [vp, C.POINTER(Params)]
@@ -227,6 +229,14 @@ class Engine:
             self.close()
         except Exception:
             pass
+
+    def set_phantom(self, phantom):
+        """New densities and materials for the same dimensions (omc_set_phantom)."""
+        assert tuple(phantom["shape"]) == self.shape
+        dens = np.ascontiguousarray(phantom["density"], dtype=np.float32).ravel()
+        mat = np.ascontiguousarray(phantom["material"], dtype=np.uint8).ravel()
+        _check(lib().omc_set_phantom(self._h, dens.ctypes.data_as(C.POINTER(C.c_float)),
+                                     mat.ctypes.data_as(C.POINTER(C.c_uint8))), self._h)
 
     def set_source(self, src):
         s, keep = _source_struct(src)

@@ -38,20 +38,23 @@ def make_pairs(omc, W, ids, shape, h, n_lo, n_hi, params):
     import torch
     data = []
     t0 = time.perf_counter()
+    eng = None
+    nv = int(np.prod(shape))
+    lo = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    lo2 = torch.zeros_like(lo)
+    hi = torch.zeros_like(lo)
+    hi2 = torch.zeros_like(lo)
     for k, i in enumerate(ids):
         ph_seed, src, (s_lo, s_hi) = W.denoiser_pair(i, shape, h)
         ph = W.ellipsoid_phantom_gpu(shape, h, 12, ph_seed)
-        eng = omc.Engine(ph)
+        if eng is None:
+            eng = omc.Engine(ph)
+            eng.set_params(**params)
+        else:
+            eng.set_phantom(ph)
         eng.set_source(src)
-        eng.set_params(**params)
-        nv = int(np.prod(shape))
-        lo = torch.zeros(nv, dtype=torch.float64, device="cuda")
-        lo2 = torch.zeros_like(lo)
-        hi = torch.zeros_like(lo)
-        hi2 = torch.zeros_like(lo)
         eng.run_device(n_lo, s_lo, 0, lo, lo2)
         eng.run_device(n_hi, s_hi, 0, hi, hi2)
-        eng.close()
         B = 10
         sig = torch.sqrt(torch.clamp(lo2 / B - lo * lo, min=0) / (B - 1))
         rho = torch.tensor(ph["density"].ravel(), device="cuda")
@@ -60,6 +63,8 @@ def make_pairs(omc, W, ids, shape, h, n_lo, n_hi, params):
                      "src": src, "ph_seed": ph_seed})
         if (k + 1) % 50 == 0 or k + 1 == len(ids):
             log(f"[data] {k + 1}/{len(ids)} pairs, {time.perf_counter() - t0:.1f} s")
+    if eng is not None:
+        eng.close()
     return data
 
 

@@ -222,3 +222,22 @@ def test_run_device_torch(omc, W):
     d, _ = eng.run(300, seed=1)
     np.testing.assert_allclose(dt.cpu().numpy().reshape(d.shape), d, rtol=1e-9, atol=1e-15)
     eng.close()
+
+
+def test_set_phantom_equals_fresh_context(omc, W):
+    """Replacing the phantom of a context (same dimensions) gives the run a
+    fresh context on the new phantom gives: identical counters, same dose."""
+    a = W.ellipsoid_phantom((24, 32, 32), 0.5, n_ell=5, seed=1)
+    b = W.ellipsoid_phantom((24, 32, 32), 0.5, n_ell=5, seed=2)
+    src = W.photon_beam((4.0, 4.0), (8.0, 8.0), spectrum=W.spectrum_6mv())
+    d_ref, _, c_ref = gpu_run(omc, b, src, 20_000, seed=4, parity_fp64=1)
+    eng = omc.Engine(a)
+    eng.set_source(src)
+    eng.set_params(parity_fp64=1)
+    eng.run(5000, seed=4)
+    eng.set_phantom(b)
+    d, _ = eng.run(20_000, seed=4)
+    c = eng.counters()
+    eng.close()
+    assert {k: c[k] for k in INT_COUNTERS} == {k: c_ref[k] for k in INT_COUNTERS}
+    np.testing.assert_allclose(d, d_ref, rtol=1e-9, atol=1e-12 * d_ref.max())
