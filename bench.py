@@ -81,7 +81,7 @@ def denoiser_flops(n):
 # chunk (0 = 2^24), work-groups per CU (what omc_autotune picks on MI355X; the
 # --autotune flag re-runs it)
 SHAPES = {
-    "slab_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 8},
+    "slab_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
     "water_e15": {"graph_depth": 8, "chunk_histories": 0, "blocks_per_cu": 4},
     "halfslab_e15": {"graph_depth": 6, "chunk_histories": 0, "blocks_per_cu": 8},
 }
@@ -206,6 +206,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=-1)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--straggler-lanes", type=int, default=-1)
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with omc_autotune before the warm-up")
     ap.add_argument("--no-timing-pass", action="store_true",
@@ -260,6 +261,8 @@ def main():
         shape["blocks_per_cu"] = args.blocks_per_cu
     if args.block_size:
         shape["block_size"] = args.block_size
+    if args.straggler_lanes >= 0:
+        shape["straggler_lanes"] = args.straggler_lanes
     eng = omc.Engine(ph)
     eng.set_source(src)
     eng.set_params(parity_fp64=int(args.parity_fp64), **shape)
@@ -310,7 +313,7 @@ def main():
                       "tally": "fp64",
                       "launch": {k: params[k] for k in ("block_size", "blocks_per_cu",
                                                         "chunk_histories", "graph_depth",
-                                                        "queue_factor")}}}
+                                                        "queue_factor", "straggler_lanes")}}}
     if not beamlets:
         # time to 1 % sigma at Dmax from the last step's batch estimate
         d = dose.cpu().numpy()
@@ -342,7 +345,8 @@ def main():
         out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in kt.items()}
         out["launches_per_step"] = {k: v[1] / args.steps for k, v in kt.items()}
         out["events_per_history"] = {k: units[k] / (n * args.steps) for k in
-                                     ("ph_flights", "ph_compton", "el_steps", "el_moller")}
+                                     ("ph_flights", "ph_compton", "el_steps", "el_moller",
+                                      "set_aside")}
         out["roofline"] = roofline_of(kt, units)
     out["max_steps_per_particle"] = c["max_steps"]
     out["watchdog"] = c["watchdog"]

@@ -111,6 +111,10 @@ typedef struct {
     double sparse_threshold; /* omc_run_beamlets keeps a voxel when its dose exceeds this
                                 fraction of the beamlet's largest voxel dose; 0 = every voxel
                                 with a positive FP32 dose (0) */
+    int straggler_lanes;     /* in a generation of more than 4 records per lane, a wave whose
+                                input is used up and that has at most this many live lanes
+                                left moves them, unchanged, to the next generation of their
+                                type, where they run packed into full waves; 0 = off (16) */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */
@@ -123,6 +127,7 @@ typedef struct {
     uint64_t queue_hwm_ph, queue_hwm_el; /* largest queue occupancy seen */
     uint32_t iterations;                 /* photon/electron generations launched */
     uint32_t max_steps;                  /* most steps taken by one particle */
+    uint64_t set_aside;                  /* particles moved to a later generation mid-track */
 } omc_counters;
 
 /* Per-kernel timing of the last run (params.timing == 1), HIP events on the

@@ -9,8 +9,9 @@
 //   queues      four structure-of-arrays particle queues (photon cur/next,
 //               electron cur/next), each {x,y,z,u,v,w,E} R, voxel u32 packed
 //               (ix | iy<<10 | iz<<20), history u32, particle id 2 x u32,
-//               tag u32 (type | tally cell << 8); a control block of
-//               {count, head} per queue
+//               tag u32 (type | resumed 0x80 | tally cell << 8), and for
+//               particles set aside mid-track their stream position u32 and
+//               one R of step state; a control block of {count, head} per queue
 //   tally       one f64[nvox] grid per tally cell (the one FP64 step on the
 //               GPU): a cell is a batch of a plain run or a beamlet of a
 //               batched-beamlet run
@@ -46,6 +47,7 @@ enum Counter : int {
     C_PUSH_EL,
     C_SRC_MISS,
     C_WATCHDOG,
+    C_SET_ASIDE,
     kNumCounters
 };
 
@@ -64,7 +66,12 @@ struct QueueView {
     uint32_t* hist;
     uint32_t* qlo;
     uint32_t* qhi;
-    uint32_t* tag;    // type | cell << 8; kHoleTag for a reserved, unfilled slot
+    uint32_t* tag;    // type | resumed (0x80) | cell << 8; kHoleTag for a reserved, unfilled slot
+    // state of a particle set aside mid-track (tag bit 0x80): stream position
+    // in words, and the remaining hard-event mean free paths (electrons) or
+    // the pending-Compton flag (photons)
+    uint32_t* aux_pos;
+    R* aux_f;
     uint32_t* count;  // number of records written (atomic append)
     uint32_t* head;   // next record to hand out (atomic take)
     uint32_t cap;
@@ -174,6 +181,7 @@ struct KernelArgs {
     uint32_t src_count;
     int chunk;            // records a wave takes from the input queue at once
     int min_grid;         // fewest work-groups a transport generation keeps
+    int spill_lanes;      // a wave with at most this many live lanes left sets them aside (0: off)
 };
 
 // LDS bytes a transport work-group stages (tables of all materials).

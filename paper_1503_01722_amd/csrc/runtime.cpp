@@ -279,7 +279,7 @@ int ensure_queues(omc_ctx* c, DeviceQueues<R>& Q, uint32_t cap_ph, uint32_t cap_
     // with no padding between arrays, so the layout below is exactly `bytes`
     cap_ph = uint32_t(std::min<uint64_t>((uint64_t(cap_ph) + 63) & ~uint64_t(63), 0x7fffffc0u));
     cap_el = uint32_t(std::min<uint64_t>((uint64_t(cap_el) + 63) & ~uint64_t(63), 0x7fffffc0u));
-    const size_t per = 7 * sizeof(R) + 5 * sizeof(uint32_t);
+    const size_t per = 8 * sizeof(R) + 6 * sizeof(uint32_t);
     const size_t bytes = (size_t(cap_ph) * 2 + size_t(cap_el) * 2) * per;
     if (hipMalloc(&Q.mem, bytes) != hipSuccess) {
         Q.mem = nullptr;
@@ -309,6 +309,8 @@ int ensure_queues(omc_ctx* c, DeviceQueues<R>& Q, uint32_t cap_ph, uint32_t cap_
         q.qlo = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
         q.qhi = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
         q.tag = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q.aux_pos = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q.aux_f = reinterpret_cast<R*>(take(cap * sizeof(R)));
         q.cap = cap;
         q.count = c->d_ctrl + 2 * k;
         q.head = c->d_ctrl + 2 * k + 1;
@@ -423,7 +425,8 @@ uint64_t omc_counters::*const kCounterField[omc::kNumCounters] = {
     &omc_counters::el_hard_fict, &omc_counters::el_moller,    &omc_counters::el_brems,
     &omc_counters::el_absorbed, &omc_counters::el_escaped,    &omc_counters::el_boundary,
     &omc_counters::el_hinge_trunc, &omc_counters::pos_annihil, &omc_counters::push_ph,
-    &omc_counters::push_el,     &omc_counters::src_miss,      &omc_counters::watchdog};
+    &omc_counters::push_el,     &omc_counters::src_miss,      &omc_counters::watchdog,
+    &omc_counters::set_aside};
 
 // ------------------------------------------------------------------- sources
 // Checks a source as omc_set_source documents and returns its spectrum as bin
@@ -672,6 +675,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     a.run = c->d_run;
     a.chunk = 64;
     a.min_grid = c->cu_count;
+    a.spill_lanes = P.straggler_lanes;
 
     const int block = P.block_size;
     const int tgrid = c->cu_count * P.blocks_per_cu;
@@ -1144,6 +1148,7 @@ void omc_default_params(omc_params* p)
     p->graph_depth = 0;
     p->beamlet_group = 0;
     p->sparse_threshold = 0.0;
+    p->straggler_lanes = 16;
 }
 
 int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
@@ -1278,6 +1283,8 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
         return fail(c, OMC_EINVAL, "launch shape out of range");
     if (!(p->sparse_threshold >= 0.0 && p->sparse_threshold < 1.0))
         return fail(c, OMC_EINVAL, "sparse_threshold must be in [0, 1)");
+    if (p->straggler_lanes < 0 || p->straggler_lanes > 63)
+        return fail(c, OMC_EINVAL, "straggler_lanes must be in 0..63");
     c->prm = *p;
     return OMC_OK;
 }

@@ -61,7 +61,7 @@ class Params(C.Structure):
                 ("csda_mode", C.c_int), ("block_size", C.c_int), ("blocks_per_cu", C.c_int),
                 ("chunk_histories", C.c_int), ("queue_factor", C.c_int), ("timing", C.c_int),
                 ("graph_depth", C.c_int), ("beamlet_group", C.c_int),
-                ("sparse_threshold", C.c_double)]
+                ("sparse_threshold", C.c_double), ("straggler_lanes", C.c_int)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -89,7 +89,8 @@ class Counters(C.Structure):
     _fields_ = ([(n, C.c_uint64) for n in COUNTER_INT + COUNTER_EXTRA]
                 + [(n, C.c_double) for n in COUNTER_FP]
                 + [("queue_hwm_ph", C.c_uint64), ("queue_hwm_el", C.c_uint64),
-                   ("iterations", C.c_uint32), ("max_steps", C.c_uint32)])
+                   ("iterations", C.c_uint32), ("max_steps", C.c_uint32),
+                   ("set_aside", C.c_uint64)])
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -264,3 +264,48 @@ def test_full_size_beamlets_sampled(omc, W):
         d = d.ravel()
         np.testing.assert_allclose(g, d.astype(np.float32), rtol=1e-5, atol=1e-7 * d.max())
     eng.close()
+
+
+# ------------------------------------------------------ stragglers set aside
+def test_fp64_set_aside_parity_with_oracle(omc, orc, W):
+    """A generation large enough (several records per lane of a one-work-group-
+    per-CU grid) moves its stragglers to the next generation with their exact
+    stream position and step state: the counters still equal the oracle's,
+    and equal a run that keeps them."""
+    ph = W.slab_phantom(32, 1.0)
+    src = W.config("slab_6mv")[1]
+    n = 400_000
+    print(f"[fp64 set-aside] slab 32^3 n={n}", flush=True)
+    eng = engine(omc, ph, src, parity_fp64=1, blocks_per_cu=1, straggler_lanes=40)
+    d, _ = eng.run(n, seed=8, h0=11)
+    c = eng.counters()
+    eng.set_params(straggler_lanes=0)
+    d0, _ = eng.run(n, seed=8, h0=11)
+    c0 = eng.counters()
+    eng.close()
+    report("set-aside", moved=c["set_aside"], iterations=c["iterations"],
+           iterations_without=c0["iterations"])
+    assert c["set_aside"] > 0 and c0["set_aside"] == 0
+    assert ints(c) == ints(c0)
+    od, _, oc = orc.run(ph, src, n, seed=8, h0=11)
+    assert ints(c) == ints(oc)
+    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * od.max())
+    np.testing.assert_allclose(d, d0, rtol=1e-9, atol=1e-12 * d0.max())
+
+
+def test_fp32_set_aside_electrons_and_graph(omc, W):
+    """15 MeV electrons (long tracks, many deltas) in FP32, graph mode with
+    carry-over, stragglers set aside or not: the same particles throughout."""
+    ph, src, _ = W.config("water_e15")
+    n = 300_000
+    runs = []
+    for lanes, depth in ((0, 0), (48, 0), (48, 3)):
+        eng = engine(omc, ph, src, blocks_per_cu=1, straggler_lanes=lanes, graph_depth=depth)
+        d, _ = eng.run(n, seed=3)
+        runs.append((d, eng.counters()))
+        eng.close()
+    report("electrons", moved=[r[1]["set_aside"] for r in runs])
+    assert runs[1][1]["set_aside"] > 0
+    for d, c in runs[1:]:
+        assert ints(c) == ints(runs[0][1])
+        np.testing.assert_allclose(d, runs[0][0], rtol=1e-9, atol=1e-12 * d.max())
