@@ -110,6 +110,24 @@ def cpu_baseline(ph, src, target_s, threads):
                       f"{dt:.1f} s"}
 
 
+def measured_traffic(kernel):
+    """HBM-side bytes per launch of `kernel` from the committed counter passes
+    (profiles/transport_counters.json), or None when the kernel sources have
+    changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "transport_counters.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["kernels"][kernel]["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline_of(kt, units):
     """ALU roofline of the dominant transport kernel from per-kernel HIP-event
     times kt and the event counters units of the same steps."""
@@ -120,7 +138,8 @@ def roofline_of(kt, units):
     achieved = ops / t_dom / 1e12
     return {"bound": "alu", "kernel": f"{dom}_kernel", "achieved": achieved,
             "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "frac": achieved / PEAK_ALU_TOPS,
-            "traffic": None, "launches": launches, "avg_launch_ms": kt[dom][0] / launches,
+            "traffic": measured_traffic(f"{dom}_kernel"), "traffic_unit": "bytes per launch",
+            "launches": launches, "avg_launch_ms": kt[dom][0] / launches,
             "ops_per_launch": ops / launches}
 
 
