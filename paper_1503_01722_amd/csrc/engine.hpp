@@ -58,6 +58,7 @@ enum PType : int { PT_PHOTON = 0, PT_ELECTRON = 1, PT_POSITRON = 2 };
 constexpr uint32_t kResBlockSlots = 128;  // output slots a wave reserves per atomic
 constexpr int kTabNE = 512;
 constexpr int kTabNA = 512;
+constexpr int kRangeCells = 1024;  // range-inverse index cells per material
 
 template <typename R>
 struct QueueView {
@@ -90,12 +91,16 @@ template <typename R>
 struct TableView {
     const R* ph;      // [n_mats][NE][4]
     const R* muhat;   // [NE]
-    const R* el;      // [n_mats][NE][4]
-    const R* K1;      // [n_mats][NE]
+    const R* el;      // [n_mats][NE][4]: K1, sigma_hat, sigma_M, sigma_B
+    const R* rtab;    // [n_mats][NE]: CSDA range R(E)
+    const uint16_t* ridx;  // [n_mats][kRangeCells]: range node of each range cell
     const R* msA;     // [NA]
     const R* Rabs;    // [n_mats]
     int n_mats;
     R L0, DL, INV;    // energy grid
+    // range cells: the FP32 bit pattern of R shifted right by rshift, minus
+    // rbase, clamped to [0, rcells-1]; a monotone pseudo-logarithm of R
+    uint32_t rshift, rbase, rcells;
     R XLO, XHI, XINV; // multiple-scattering grid
     R ELo, EHi;
 };
@@ -194,7 +199,8 @@ template <typename R>
 inline size_t electron_lds_bytes(int n_mats)
 {
     return 4 * sizeof(R) * size_t(n_mats) * kTabNE + sizeof(R) * size_t(n_mats) * kTabNE +
-           sizeof(R) * kTabNA + sizeof(R) * 8;
+           sizeof(R) * kTabNA + sizeof(R) * ((size_t(n_mats) + 7) & ~size_t(7)) +
+           sizeof(uint16_t) * size_t(n_mats) * kRangeCells;
 }
 
 // Host-side launchers (one instantiation per precision).

@@ -44,10 +44,12 @@ struct DeviceTables {
     R* ph = nullptr;
     R* muhat = nullptr;
     R* el = nullptr;
-    R* K1 = nullptr;
+    R* rtab = nullptr;
+    uint16_t* ridx = nullptr;
     R* msA = nullptr;
     R* Rabs = nullptr;
     R* edges = nullptr;
+    uint32_t rshift = 0, rbase = 0, rcells = 1;
     bool valid = false;
 };
 
@@ -156,7 +158,8 @@ void free_tables(DeviceTables<R>& t)
     dfree(t.ph);
     dfree(t.muhat);
     dfree(t.el);
-    dfree(t.K1);
+    dfree(t.rtab);
+    dfree(t.ridx);
     dfree(t.msA);
     dfree(t.Rabs);
     dfree(t.edges);
@@ -228,6 +231,49 @@ int upload(omc_ctx* c, R*& dst, const std::vector<R>& v)
     return OMC_OK;
 }
 
+// Index of the range inverse: cell k of the range axis holds the FP32 values
+// whose bit pattern, shifted right by rshift, equals rbase + k (positive floats
+// order as their bit patterns, so cells are monotone in R and each spans
+// 1/2^(23-rshift) of an octave). The entry is the largest node j <= NE-2 with
+// R_j at or below the cell's smallest value; the device walks from there to
+// the exact bracket. The axis starts at R_1 (the range vanishes at the lowest
+// energy node, and every value below R_1 falls in the first cell); the shift
+// is the smallest that fits every material's axis in kRangeCells cells.
+template <typename R>
+void range_index(const std::vector<R>& rtab, int nm, DeviceTables<R>& t,
+                 std::vector<uint16_t>& ridx)
+{
+    const int NE = omc::kNE;
+    auto bits = [](double v) {
+        const float f = float(v);
+        uint32_t b;
+        std::memcpy(&b, &f, sizeof b);
+        return b;
+    };
+    uint32_t lo = ~0u, hi = 0u;
+    for (int m = 0; m < nm; ++m) {
+        lo = std::min(lo, bits(double(rtab[size_t(m) * NE + 1])));  // R_0 = 0
+        hi = std::max(hi, bits(double(rtab[size_t(m) * NE + NE - 1])));
+    }
+    uint32_t shift = 8;
+    while (((hi >> shift) - (lo >> shift)) + 1 > uint32_t(omc::kRangeCells)) ++shift;
+    t.rshift = shift;
+    t.rbase = lo >> shift;
+    t.rcells = (hi >> shift) - t.rbase + 1;
+    ridx.assign(size_t(nm) * omc::kRangeCells, 0);
+    for (int m = 0; m < nm; ++m) {
+        const R* r = rtab.data() + size_t(m) * NE;
+        int j = 0;
+        for (uint32_t k = 0; k < uint32_t(omc::kRangeCells); ++k) {
+            const uint32_t cb = (t.rbase + std::min(k, t.rcells - 1)) << shift;
+            float cf;
+            std::memcpy(&cf, &cb, sizeof cf);
+            while (j < NE - 2 && double(r[j + 1]) <= double(cf)) ++j;
+            ridx[size_t(m) * omc::kRangeCells + k] = uint16_t(j);
+        }
+    }
+}
+
 template <typename R>
 int device_tables(omc_ctx* c, DeviceTables<R>& t)
 {
@@ -235,7 +281,7 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
     if (t.valid) return OMC_OK;
     const int nm = int(c->mats.size());
     const int NE = omc::kNE;
-    std::vector<R> ph(size_t(nm) * NE * 4), el(size_t(nm) * NE * 4), K1(size_t(nm) * NE),
+    std::vector<R> ph(size_t(nm) * NE * 4), el(size_t(nm) * NE * 4), rtab(size_t(nm) * NE),
         muhat(NE), msA(omc::kNA), Rabs(nm);
     for (int m = 0; m < nm; ++m) {
         const auto& T = c->tabs[m];
@@ -245,11 +291,11 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
             ph[o + 1] = R(T.muC[i]);
             ph[o + 2] = R(T.muPE[i]);
             ph[o + 3] = R(0);
-            el[o + 0] = R(T.R[i]);
+            el[o + 0] = R(T.K1[i]);
             el[o + 1] = R(T.sigHat[i]);
             el[o + 2] = R(T.sigM[i]);
             el[o + 3] = R(T.sigB[i]);
-            K1[size_t(m) * NE + i] = R(T.K1[i]);
+            rtab[size_t(m) * NE + i] = R(T.R[i]);
         }
         Rabs[m] = R(c->Rabs[m]);
     }
@@ -261,8 +307,11 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
         muhat[i] = R(mx);
     }
     for (int j = 0; j < omc::kNA; ++j) msA[j] = R(c->ms[j]);
+    std::vector<uint16_t> ridx;
+    range_index(rtab, nm, t, ridx);
     int rc;
-    if ((rc = upload(c, t.ph, ph)) || (rc = upload(c, t.el, el)) || (rc = upload(c, t.K1, K1)) ||
+    if ((rc = upload(c, t.ph, ph)) || (rc = upload(c, t.el, el)) ||
+        (rc = upload(c, t.rtab, rtab)) || (rc = upload(c, t.ridx, ridx)) ||
         (rc = upload(c, t.muhat, muhat)) || (rc = upload(c, t.msA, msA)) ||
         (rc = upload(c, t.Rabs, Rabs)))
         return rc;
@@ -650,7 +699,11 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     a.tab.ph = T.ph;
     a.tab.muhat = T.muhat;
     a.tab.el = T.el;
-    a.tab.K1 = T.K1;
+    a.tab.rtab = T.rtab;
+    a.tab.ridx = T.ridx;
+    a.tab.rshift = T.rshift;
+    a.tab.rbase = T.rbase;
+    a.tab.rcells = T.rcells;
     a.tab.msA = T.msA;
     a.tab.Rabs = T.Rabs;
     a.tab.n_mats = int(c->mats.size());
