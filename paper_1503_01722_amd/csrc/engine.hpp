@@ -85,6 +85,7 @@ struct PhantomView {
     int nx, ny, nz;
     R hx, hy, hz;
     R ihx, ihy, ihz;  // 1/h (production transport only)
+    R fnx, fny, fnz;  // the dimensions in the transport precision
 };
 
 template <typename R>

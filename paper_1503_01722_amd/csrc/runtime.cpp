@@ -694,7 +694,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     omc::KernelArgs<R> a;
     std::memset(&a, 0, sizeof a);
     a.ph = {c->d_rho, c->d_mat, c->nx, c->ny, c->nz, R(c->dx), R(c->dy), R(c->dz),
-            R(1.0 / c->dx), R(1.0 / c->dy), R(1.0 / c->dz)};
+            R(1.0 / c->dx), R(1.0 / c->dy), R(1.0 / c->dz), R(c->nx), R(c->ny), R(c->nz)};
     const omc::EnergyGrid g = omc::energy_grid();
     a.tab.ph = T.ph;
     a.tab.muhat = T.muhat;
