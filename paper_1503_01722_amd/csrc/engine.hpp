@@ -92,7 +92,8 @@ template <typename R>
 struct TableView {
     const R* ph;      // [n_mats][NE][4]
     const R* muhat;   // [NE]
-    const R* el;      // [n_mats][NE][4]: K1, sigma_hat, sigma_M, sigma_B
+    const R* el;      // [n_mats][NE][2]: K1, sigma_hat (staged in LDS)
+    const R* hard;    // [n_mats][NE][2]: sigma_M, sigma_B (global memory)
     const R* rtab;    // [n_mats][NE]: CSDA range R(E)
     const uint16_t* ridx;  // [n_mats][kRangeCells]: range node of each range cell
     const R* msA;     // [NA]
@@ -199,7 +200,7 @@ inline size_t photon_lds_bytes(int n_mats)
 template <typename R>
 inline size_t electron_lds_bytes(int n_mats)
 {
-    return 4 * sizeof(R) * size_t(n_mats) * kTabNE + sizeof(R) * size_t(n_mats) * kTabNE +
+    return 2 * sizeof(R) * size_t(n_mats) * kTabNE + sizeof(R) * size_t(n_mats) * kTabNE +
            sizeof(R) * kTabNA + sizeof(R) * ((size_t(n_mats) + 7) & ~size_t(7)) +
            sizeof(uint16_t) * size_t(n_mats) * kRangeCells;
 }

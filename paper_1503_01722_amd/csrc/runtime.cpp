@@ -44,6 +44,7 @@ struct DeviceTables {
     R* ph = nullptr;
     R* muhat = nullptr;
     R* el = nullptr;
+    R* hard = nullptr;
     R* rtab = nullptr;
     uint16_t* ridx = nullptr;
     R* msA = nullptr;
@@ -158,6 +159,7 @@ void free_tables(DeviceTables<R>& t)
     dfree(t.ph);
     dfree(t.muhat);
     dfree(t.el);
+    dfree(t.hard);
     dfree(t.rtab);
     dfree(t.ridx);
     dfree(t.msA);
@@ -281,8 +283,8 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
     if (t.valid) return OMC_OK;
     const int nm = int(c->mats.size());
     const int NE = omc::kNE;
-    std::vector<R> ph(size_t(nm) * NE * 4), el(size_t(nm) * NE * 4), rtab(size_t(nm) * NE),
-        muhat(NE), msA(omc::kNA), Rabs(nm);
+    std::vector<R> ph(size_t(nm) * NE * 4), el(size_t(nm) * NE * 2), hard(size_t(nm) * NE * 2),
+        rtab(size_t(nm) * NE), muhat(NE), msA(omc::kNA), Rabs(nm);
     for (int m = 0; m < nm; ++m) {
         const auto& T = c->tabs[m];
         for (int i = 0; i < NE; ++i) {
@@ -291,10 +293,11 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
             ph[o + 1] = R(T.muC[i]);
             ph[o + 2] = R(T.muPE[i]);
             ph[o + 3] = R(0);
-            el[o + 0] = R(T.K1[i]);
-            el[o + 1] = R(T.sigHat[i]);
-            el[o + 2] = R(T.sigM[i]);
-            el[o + 3] = R(T.sigB[i]);
+            const size_t o2 = (size_t(m) * NE + i) * 2;
+            el[o2 + 0] = R(T.K1[i]);
+            el[o2 + 1] = R(T.sigHat[i]);
+            hard[o2 + 0] = R(T.sigM[i]);
+            hard[o2 + 1] = R(T.sigB[i]);
             rtab[size_t(m) * NE + i] = R(T.R[i]);
         }
         Rabs[m] = R(c->Rabs[m]);
@@ -310,7 +313,7 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
     std::vector<uint16_t> ridx;
     range_index(rtab, nm, t, ridx);
     int rc;
-    if ((rc = upload(c, t.ph, ph)) || (rc = upload(c, t.el, el)) ||
+    if ((rc = upload(c, t.ph, ph)) || (rc = upload(c, t.el, el)) || (rc = upload(c, t.hard, hard)) ||
         (rc = upload(c, t.rtab, rtab)) || (rc = upload(c, t.ridx, ridx)) ||
         (rc = upload(c, t.muhat, muhat)) || (rc = upload(c, t.msA, msA)) ||
         (rc = upload(c, t.Rabs, Rabs)))
@@ -699,6 +702,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     a.tab.ph = T.ph;
     a.tab.muhat = T.muhat;
     a.tab.el = T.el;
+    a.tab.hard = T.hard;
     a.tab.rtab = T.rtab;
     a.tab.ridx = T.ridx;
     a.tab.rshift = T.rshift;
