@@ -86,6 +86,9 @@ struct PhantomView {
     R hx, hy, hz;
     R ihx, ihy, ihz;  // 1/h (production transport only)
     R fnx, fny, fnz;  // the dimensions in the transport precision
+    // density bits and material id of each voxel side by side: the transport
+    // kernels gather both with one 8-byte load (one cache line)
+    const uint2* vox;
 };
 
 template <typename R>

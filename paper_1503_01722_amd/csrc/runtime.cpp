@@ -82,6 +82,7 @@ struct omc_ctx {
     int cu_count = 0;
     float* d_rho = nullptr;
     uint8_t* d_mat = nullptr;
+    uint32_t* d_vox = nullptr;  // [nvox][2]: density bits, material id
     double* d_grid = nullptr;
     size_t grid_cells = 0;      // tally cells d_grid holds (nvox doubles each)
     char* d_src = nullptr;      // beams, history prefix, spectra of the current job
@@ -697,7 +698,8 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     omc::KernelArgs<R> a;
     std::memset(&a, 0, sizeof a);
     a.ph = {c->d_rho, c->d_mat, c->nx, c->ny, c->nz, R(c->dx), R(c->dy), R(c->dz),
-            R(1.0 / c->dx), R(1.0 / c->dy), R(1.0 / c->dz), R(c->nx), R(c->ny), R(c->nz)};
+            R(1.0 / c->dx), R(1.0 / c->dy), R(1.0 / c->dz), R(c->nx), R(c->ny), R(c->nz),
+            reinterpret_cast<const uint2*>(c->d_vox)};
     const omc::EnergyGrid g = omc::energy_grid();
     a.tab.ph = T.ph;
     a.tab.muhat = T.muhat;
@@ -1208,6 +1210,8 @@ void omc_default_params(omc_params* p)
     p->straggler_lanes = 16;
 }
 
+int upload_phantom(omc_ctx* c);
+
 int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
                const float* density, const uint8_t* material, const omc_material* mats,
                int n_mats)
@@ -1273,14 +1277,29 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
               hipHostMalloc(&c->h_ctrl, 64 * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->d_run, sizeof(omc::RunDesc)) == hipSuccess &&
               hipHostMalloc(&c->h_run, sizeof(omc::RunDesc)) == hipSuccess;
-    ok = ok && hipMemcpy(c->d_rho, c->rho.data(), c->nvox * sizeof(float), hipMemcpyHostToDevice) ==
-                   hipSuccess;
-    ok = ok && hipMemcpy(c->d_mat, c->mat.data(), c->nvox, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMalloc(&c->d_vox, c->nvox * 2 * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && upload_phantom(c) == OMC_OK;
     if (!ok) {
         omc_destroy(c);
         return fail(nullptr, OMC_ENOMEM, "device allocation or upload failed");
     }
     *out = c;
+    return OMC_OK;
+}
+
+// Densities and materials to the device: the two plain arrays (dose
+// conversion, compaction) and the interleaved voxel records of the transport.
+int upload_phantom(omc_ctx* c)
+{
+    std::vector<uint32_t> vox(c->nvox * 2);
+    for (size_t v = 0; v < c->nvox; ++v) {
+        std::memcpy(&vox[2 * v], &c->rho[v], sizeof(float));
+        vox[2 * v + 1] = c->mat[v];
+    }
+    HIP_TRY(c, hipMemcpy(c->d_rho, c->rho.data(), c->nvox * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_mat, c->mat.data(), c->nvox, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_vox, vox.data(), vox.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice));
     return OMC_OK;
 }
 
@@ -1299,8 +1318,7 @@ int omc_set_phantom(omc_ctx* c, const float* density, const uint8_t* material)
     c->rho.assign(density, density + c->nvox);
     c->mat.assign(material, material + c->nvox);
     c->rho_max = rmax;
-    HIP_TRY(c, hipMemcpy(c->d_rho, c->rho.data(), c->nvox * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_mat, c->mat.data(), c->nvox, hipMemcpyHostToDevice));
+    if (int rc = upload_phantom(c)) return rc;
     // the majorant depends on rho_max: rebuild the device tables on the next run
     c->t32.valid = false;
     c->t64.valid = false;
@@ -1671,6 +1689,7 @@ void omc_destroy(omc_ctx* c)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     dfree(c->d_rho);
     dfree(c->d_mat);
+    dfree(c->d_vox);
     dfree(c->d_src);
     dfree(c->d_run);
     dfree(c->d_cscratch);
