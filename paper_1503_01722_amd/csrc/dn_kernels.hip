@@ -176,6 +176,179 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvParams p)
     }
 }
 
+// ------------------------------------------------ 3x3x3 convolution, LDS tile
+// The same GEMM as conv_kernel<G_CONV3, NT> for inputs of 8, 16, 32 or 48
+// channels, with the input staged once per work-group instead of gathered per
+// tap. A work-group owns an output block of BZ x BY x 16 voxels (x fastest):
+// it copies the block's input with its one-voxel halo, (BZ+2) x (BY+2) x 18
+// voxels, into LDS (channels-last, voxel pitch an odd number of 16-byte
+// chunks so that 16 consecutive voxels fall in distinct bank groups; zeros
+// outside the volume), then computes the block in passes of 16 row tiles:
+// wave w takes row tiles 4w .. 4w+3 of the pass (a row tile is 16 voxels
+// along x at one (z, y); the four are consecutive in y). With the channel
+// count a compile-time constant, the LDS offset of every (reduction block,
+// lane group) is a constant and the row tile's an immediate. The reduction
+// order over (tap, channel) blocks of 32 is that of conv_kernel, so both give
+// the same sums.
+constexpr int kTileX = 16;
+
+template <int CIN>
+struct TileShape {
+    static constexpr int BZ = CIN <= 8 ? 8 : 4;
+    static constexpr int BY = CIN <= 16 ? 8 : 4;
+    static constexpr int SY = BY + 2, SX = kTileX + 2;
+    static constexpr int PC = (CIN / 8) | 1;  // 16-byte chunks per staged voxel
+    static constexpr int K = 27 * CIN;
+    static constexpr int KB = (K + 31) / 32;
+    static constexpr size_t lds = size_t(BZ + 2) * SY * SX * PC * 16;
+    // LDS chunk offset of reduction index k0 (a multiple of 8) from the
+    // haloed block's origin: tap (dz, dy, dx) reads voxel (z+dz, y+dy, x+dx)
+    static constexpr int chunk(int k0)
+    {
+        if (k0 >= K) return 0;
+        const int t = k0 / CIN, ci = k0 % CIN;
+        return (((t / 9) * SY + (t / 3) % 3) * SX + t % 3) * PC + ci / 8;
+    }
+};
+
+template <int NT, int CIN>
+__global__ void __launch_bounds__(256) conv3_tile_kernel(ConvParams p)
+{
+    using S = TileShape<CIN>;
+    constexpr int BZ = S::BZ, BY = S::BY, SY = S::SY, SX = S::SX, PC = S::PC, KB = S::KB;
+    static_assert((BZ * BY) % 16 == 0 && BY % 4 == 0, "whole passes; row tiles in y fours");
+    extern __shared__ __align__(16) uint4 tile[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int nxt = (p.out.nx + kTileX - 1) / kTileX;
+    const int x0 = (int(blockIdx.x) % nxt) * kTileX;
+    const int y0 = (int(blockIdx.x) / nxt) * BY;
+    const int z0 = int(blockIdx.y) * BZ;
+    const int nt0 = int(blockIdx.z) * NT;
+
+    // stage: piece q = (voxel of the haloed block, chunk of 8 channels); each
+    // thread issues kSB loads before it writes any, so they are in flight together
+    constexpr int CG = CIN / 8;
+    constexpr int PIECES = (BZ + 2) * SY * SX * CG;
+    constexpr int kSB = 8;
+    for (int q0 = threadIdx.x; q0 < PIECES; q0 += 256 * kSB) {
+        uint4 raw[kSB];
+#pragma unroll
+        for (int u = 0; u < kSB; ++u) {
+            const int q = q0 + 256 * u;
+            raw[u] = uint4{0u, 0u, 0u, 0u};
+            if (q < PIECES) {
+                const int c = q % CG;
+                const int v = q / CG;
+                const int lx = v % SX, ly = (v / SX) % SY, lz = v / (SX * SY);
+                const int ix = x0 + lx - 1, iy = y0 + ly - 1, iz = z0 + lz - 1;
+                if (ix >= 0 && iy >= 0 && iz >= 0 && ix < p.in.nx && iy < p.in.ny &&
+                    iz < p.in.nz) {
+                    const size_t gv = (size_t(iz) * p.in.ny + iy) * p.in.nx + ix;
+                    const int ci = c * 8;
+                    const uint16_t* src =
+                        ci < p.c0 ? p.x0 + gv * p.c0 + ci : p.x1 + gv * p.c1 + (ci - p.c0);
+                    raw[u] = *reinterpret_cast<const uint4*>(src);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSB; ++u) {
+            const int q = q0 + 256 * u;
+            if (q < PIECES) tile[(q / CG) * PC + q % CG] = raw[u];
+        }
+    }
+    __syncthreads();
+
+    const uint4* bsrc = reinterpret_cast<const uint4*>(p.packed);
+    // weight fragments in groups of KU reduction blocks: the next group is
+    // loaded while the current group's products run
+    constexpr int KU = NT <= 2 ? 4 : 2;
+    auto load_b = [&](bf16x8 (&dst)[KU][NT], int kb0) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int kb = kb0 + u;
+                const uint4 raw = kb < KB ? bsrc[(size_t(nt0 + n) * KB + kb) * 64 + lane]
+                                          : uint4{0u, 0u, 0u, 0u};
+                dst[u][n] = as_bf16x8(raw);
+            }
+    };
+    for (int pass = 0; pass < BZ * BY / 16; ++pass) {
+        const int rt0 = pass * 16 + wave * 4;
+        const int lb = (((rt0 / BY) * SY + rt0 % BY) * SX + r) * PC;  // row tile s: + s*SX*PC
+        f32x4 acc[4][NT];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[s][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 b[KU][NT], bn[KU][NT];
+        load_b(b, 0);
+#pragma unroll
+        for (int kb0 = 0; kb0 < KB; kb0 += KU) {
+            if (kb0 + KU < KB) load_b(bn, kb0 + KU);
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int kb = kb0 + u;
+                if (kb >= KB) break;
+                const int o0 = S::chunk(kb * 32), o1 = S::chunk(kb * 32 + 8);
+                const int o2 = S::chunk(kb * 32 + 16), o3 = S::chunk(kb * 32 + 24);
+                const int off = lb + (g == 0 ? o0 : g == 1 ? o1 : g == 2 ? o2 : o3);
+                const bool kv = kb * 32 + g * 8 < S::K;  // false only in the last block
+                bf16x8 a[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    uint4 raw = tile[off + s * SX * PC];
+                    if (!kv) raw = uint4{0u, 0u, 0u, 0u};
+                    a[s] = as_bf16x8(raw);
+                }
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s][n] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], b[u][n], acc[s][n], 0, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < KU; ++u)
+#pragma unroll
+                for (int n = 0; n < NT; ++n) b[u][n] = bn[u][n];
+        }
+        // epilogue: lane (r, g) holds voxels x0 + 4g + i of each row tile, column r
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int rt = rt0 + s;
+            const int z = z0 + rt / BY, y = y0 + rt % BY;
+            if (z >= p.out.nz || y >= p.out.ny) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * g + i;
+                if (x >= p.out.nx) continue;
+                const size_t ov = (size_t(z) * p.out.ny + y) * p.out.nx + x;
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const int ch = (nt0 + n) * 16 + r;
+                    float v = acc[s][n][i];
+                    if (p.o.y) {
+                        if (p.o.bias) v += p.o.bias[ch];
+                        if (p.o.relu) v = fmaxf(v, 0.f);
+                        p.o.y[ov * size_t(p.N) + ch] = f2bf(v);
+                    } else if (ch < p.o.split) {
+                        float* d = p.o.g0 + ov * size_t(p.o.split) + ch;
+                        *d = p.o.acc0 ? *d + v : v;
+                    } else {
+                        const int w1 = p.N - p.o.split;
+                        float* d = p.o.g1 + ov * size_t(w1) + (ch - p.o.split);
+                        *d = p.o.acc1 ? *d + v : v;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ weight gradient
 constexpr int kWRows = 128;    // rows staged per step
 constexpr int kWPitch = 136;   // LDS row pitch in BF16 (272 bytes: 16-byte aligned rows)
@@ -554,6 +727,57 @@ int conv_launch(const ConvParams& p, dim3 grid, hipStream_t s)
     return status();
 }
 
+// Largest LDS block a tile kernel takes (48 channels: two work-groups per CU).
+constexpr size_t kTileLdsMax = 80 * 1024;
+
+template <int NT, int CIN>
+int tile_launch(const ConvParams& p, int tiles, hipStream_t s)
+{
+    using S = TileShape<CIN>;
+    static_assert(S::lds <= kTileLdsMax, "staged block within the LDS budget");
+    static bool raised = false;  // one attribute call per instantiation
+    if (!raised) {
+        if (hipFuncSetAttribute((const void*)conv3_tile_kernel<NT, CIN>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(kTileLdsMax)) != hipSuccess)
+            return -1;
+        raised = true;
+    }
+    const unsigned nxt = unsigned((p.out.nx + kTileX - 1) / kTileX);
+    const unsigned nyt = unsigned((p.out.ny + S::BY - 1) / S::BY);
+    const unsigned nzt = unsigned((p.out.nz + S::BZ - 1) / S::BZ);
+    const dim3 grid{nxt * nyt, nzt, unsigned(tiles / NT)};
+    hipLaunchKernelGGL((conv3_tile_kernel<NT, CIN>), grid, dim3(256), S::lds, s, p);
+    return status();
+}
+
+template <int CIN>
+int tile_cin(const ConvParams& p, int nt, int tiles, hipStream_t s)
+{
+    switch (nt) {
+    case 1: return tile_launch<1, CIN>(p, tiles, s);
+    case 2: return tile_launch<2, CIN>(p, tiles, s);
+    case 3: return tile_launch<3, CIN>(p, tiles, s);
+    case 4: return tile_launch<4, CIN>(p, tiles, s);
+    default: return -1;
+    }
+}
+
+// The LDS tile path of a 3x3x3 convolution for the channel counts it is
+// built for; -1 for others (the gather kernel then runs).
+bool conv3_tiles(int cin) { return cin == 8 || cin == 16 || cin == 32 || cin == 48; }
+
+int conv3_tiled(const ConvParams& p, int nt, int tiles, hipStream_t s)
+{
+    switch (p.c0 + p.c1) {
+    case 8: return tile_cin<8>(p, nt, tiles, s);
+    case 16: return tile_cin<16>(p, nt, tiles, s);
+    case 32: return tile_cin<32>(p, nt, tiles, s);
+    case 48: return tile_cin<48>(p, nt, tiles, s);
+    default: return -1;
+    }
+}
+
 template <int GEOM>
 int conv_geom(const ConvParams& p, int nt, dim3 grid, hipStream_t s)
 {
@@ -632,7 +856,10 @@ int launch_conv(int geometry, const uint16_t* x0, int c0, const uint16_t* x1, in
     const dim3 grid{unsigned((p.M + 255) / 256), unsigned(tiles / nt), 1u};
     hipStream_t s = (hipStream_t)stream;
     switch (geometry) {
-    case G_CONV3: return conv_geom<G_CONV3>(p, nt, grid, s);
+    case G_CONV3:
+        if (in.nz == out.nz && in.ny == out.ny && in.nx == out.nx && conv3_tiles(c0 + c1))
+            return conv3_tiled(p, nt, tiles, s);
+        return conv_geom<G_CONV3>(p, nt, grid, s);
     case G_DOWN: return conv_geom<G_DOWN>(p, nt, grid, s);
     case G_UP: return conv_geom<G_UP>(p, nt, grid, s);
     default: return -1;
