@@ -177,25 +177,26 @@ __global__ void __launch_bounds__(256) conv_kernel(ConvParams p)
 }
 
 // ------------------------------------------------ 3x3x3 convolution, LDS tile
-// The same GEMM as conv_kernel<G_CONV3, NT> for inputs of 8, 16, 32 or 48
-// channels, with the input staged once per work-group instead of gathered per
-// tap. A work-group owns an output block of BZ x BY x 16 voxels (x fastest):
-// it copies the block's input with its one-voxel halo, (BZ+2) x (BY+2) x 18
-// voxels, into LDS (channels-last, voxel pitch an odd number of 16-byte
-// chunks so that 16 consecutive voxels fall in distinct bank groups; zeros
-// outside the volume), then computes the block in passes of 16 row tiles:
-// wave w takes row tiles 4w .. 4w+3 of the pass (a row tile is 16 voxels
-// along x at one (z, y); the four are consecutive in y). With the channel
-// count a compile-time constant, the LDS offset of every (reduction block,
-// lane group) is a constant and the row tile's an immediate. The reduction
-// order over (tap, channel) blocks of 32 is that of conv_kernel, so both give
-// the same sums.
+// The same GEMM as conv_kernel<G_CONV3, NT> for inputs of 8 to 96 channels,
+// with the input staged once per work-group instead of gathered per tap. A
+// work-group owns an output block of BZ x 4 x 16 voxels (x fastest): it
+// copies the block's input with its one-voxel halo, (BZ+2) x 6 x 18 voxels,
+// into LDS (channels-last, voxel pitch an odd number of 16-byte chunks so
+// that 16 consecutive voxels fall in distinct bank groups; zeros outside the
+// volume), then each of its four waves computes RS = BZ row tiles (a row
+// tile is 16 voxels along x at one (z, y); a wave's tiles are consecutive in
+// y). With the channel count a compile-time constant, the LDS offset of every
+// (reduction block, lane group) is a constant and the row tile's an
+// immediate. The reduction order over (tap, channel) blocks of 32 is that of
+// conv_kernel, so both give the same sums.
 constexpr int kTileX = 16;
 
 template <int CIN>
 struct TileShape {
-    static constexpr int BZ = CIN <= 8 ? 8 : 4;
-    static constexpr int BY = CIN <= 16 ? 8 : 4;
+    // 16 row tiles of 4 per wave up to 48 channels, 8 of 2 per wave above
+    static constexpr int BZ = CIN <= 48 ? 4 : 2;
+    static constexpr int BY = 4;
+    static constexpr int RS = BZ * BY / 4;  // row tiles per wave
     static constexpr int SY = BY + 2, SX = kTileX + 2;
     static constexpr int PC = (CIN / 8) | 1;  // 16-byte chunks per staged voxel
     static constexpr int K = 27 * CIN;
@@ -215,8 +216,9 @@ template <int NT, int CIN>
 __global__ void __launch_bounds__(256) conv3_tile_kernel(ConvParams p)
 {
     using S = TileShape<CIN>;
-    constexpr int BZ = S::BZ, BY = S::BY, SY = S::SY, SX = S::SX, PC = S::PC, KB = S::KB;
-    static_assert((BZ * BY) % 16 == 0 && BY % 4 == 0, "whole passes; row tiles in y fours");
+    constexpr int BZ = S::BZ, BY = S::BY, RS = S::RS, SY = S::SY, SX = S::SX, PC = S::PC;
+    constexpr int KB = S::KB;
+    static_assert(BY % RS == 0, "a wave's row tiles share z");
     extern __shared__ __align__(16) uint4 tile[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -276,12 +278,12 @@ __global__ void __launch_bounds__(256) conv3_tile_kernel(ConvParams p)
                 dst[u][n] = as_bf16x8(raw);
             }
     };
-    for (int pass = 0; pass < BZ * BY / 16; ++pass) {
-        const int rt0 = pass * 16 + wave * 4;
+    {
+        const int rt0 = wave * RS;
         const int lb = (((rt0 / BY) * SY + rt0 % BY) * SX + r) * PC;  // row tile s: + s*SX*PC
-        f32x4 acc[4][NT];
+        f32x4 acc[RS][NT];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < RS; ++s)
 #pragma unroll
             for (int n = 0; n < NT; ++n) acc[s][n] = f32x4{0.f, 0.f, 0.f, 0.f};
         bf16x8 b[KU][NT], bn[KU][NT];
@@ -297,9 +299,9 @@ __global__ void __launch_bounds__(256) conv3_tile_kernel(ConvParams p)
                 const int o2 = S::chunk(kb * 32 + 16), o3 = S::chunk(kb * 32 + 24);
                 const int off = lb + (g == 0 ? o0 : g == 1 ? o1 : g == 2 ? o2 : o3);
                 const bool kv = kb * 32 + g * 8 < S::K;  // false only in the last block
-                bf16x8 a[4];
+                bf16x8 a[RS];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
+                for (int s = 0; s < RS; ++s) {
                     uint4 raw = tile[off + s * SX * PC];
                     if (!kv) raw = uint4{0u, 0u, 0u, 0u};
                     a[s] = as_bf16x8(raw);
@@ -307,7 +309,7 @@ __global__ void __launch_bounds__(256) conv3_tile_kernel(ConvParams p)
 #pragma unroll
                 for (int n = 0; n < NT; ++n)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s)
+                    for (int s = 0; s < RS; ++s)
                         acc[s][n] =
                             __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], b[u][n], acc[s][n], 0, 0, 0);
             }
@@ -318,7 +320,7 @@ __global__ void __launch_bounds__(256) conv3_tile_kernel(ConvParams p)
         }
         // epilogue: lane (r, g) holds voxels x0 + 4g + i of each row tile, column r
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < RS; ++s) {
             const int rt = rt0 + s;
             const int z = z0 + rt / BY, y = y0 + rt % BY;
             if (z >= p.out.nz || y >= p.out.ny) continue;
@@ -727,8 +729,8 @@ int conv_launch(const ConvParams& p, dim3 grid, hipStream_t s)
     return status();
 }
 
-// Largest LDS block a tile kernel takes (48 channels: two work-groups per CU).
-constexpr size_t kTileLdsMax = 80 * 1024;
+// Largest LDS block a tile kernel takes (96 channels: one work-group per CU).
+constexpr size_t kTileLdsMax = 96 * 1024;
 
 template <int NT, int CIN>
 int tile_launch(const ConvParams& p, int tiles, hipStream_t s)
@@ -764,16 +766,40 @@ int tile_cin(const ConvParams& p, int nt, int tiles, hipStream_t s)
 }
 
 // The LDS tile path of a 3x3x3 convolution for the channel counts it is
-// built for; -1 for others (the gather kernel then runs).
-bool conv3_tiles(int cin) { return cin == 8 || cin == 16 || cin == 32 || cin == 48; }
-
-int conv3_tiled(const ConvParams& p, int nt, int tiles, hipStream_t s)
+// built for (the network's); the gather kernel runs for others.
+bool conv3_tiles(int cin)
 {
-    switch (p.c0 + p.c1) {
+    return cin == 8 || cin == 16 || cin == 32 || cin == 48 || cin == 64 || cin == 96;
+}
+
+// Column tiles per work-group: as many as divide the columns while the grid
+// still has two work-groups per CU; fewer (each restages its block) when the
+// volume is small.
+int tile_columns(int tiles, size_t blocks)
+{
+    int nt = tiles % 4 == 0 ? 4 : tiles % 3 == 0 ? 3 : tiles % 2 == 0 ? 2 : 1;
+    while (nt > 1 && blocks * size_t(tiles / nt) < 512) {
+        int next = nt - 1;
+        while (next > 1 && tiles % next) --next;
+        nt = next;
+    }
+    return nt;
+}
+
+int conv3_tiled(const ConvParams& p, int tiles, hipStream_t s)
+{
+    const int cin = p.c0 + p.c1;
+    const int bz = cin <= 48 ? 4 : 2;
+    const size_t blocks = size_t((p.out.nx + kTileX - 1) / kTileX) * ((p.out.ny + 3) / 4) *
+                          ((p.out.nz + bz - 1) / bz);
+    const int nt = tile_columns(tiles, blocks);
+    switch (cin) {
     case 8: return tile_cin<8>(p, nt, tiles, s);
     case 16: return tile_cin<16>(p, nt, tiles, s);
     case 32: return tile_cin<32>(p, nt, tiles, s);
     case 48: return tile_cin<48>(p, nt, tiles, s);
+    case 64: return tile_cin<64>(p, nt, tiles, s);
+    case 96: return tile_cin<96>(p, nt, tiles, s);
     default: return -1;
     }
 }
@@ -858,7 +884,7 @@ int launch_conv(int geometry, const uint16_t* x0, int c0, const uint16_t* x1, in
     switch (geometry) {
     case G_CONV3:
         if (in.nz == out.nz && in.ny == out.ny && in.nx == out.nx && conv3_tiles(c0 + c1))
-            return conv3_tiled(p, nt, tiles, s);
+            return conv3_tiled(p, tiles, s);
         return conv_geom<G_CONV3>(p, nt, grid, s);
     case G_DOWN: return conv_geom<G_DOWN>(p, nt, grid, s);
     case G_UP: return conv_geom<G_UP>(p, nt, grid, s);

@@ -49,6 +49,8 @@ LAYERS = [  # geometry, volume (z, y, x), c0, c1, cout: every shape the network 
     (0, (9, 19, 35), 16, 16, 16),
     (0, (7, 9, 21), 8, 0, 16),
     (0, (7, 9, 21), 48, 0, 48),
+    (0, (5, 9, 21), 64, 0, 64),
+    (0, (5, 9, 21), 48, 48, 48),
     (1, (6, 10, 12), 16, 0, 32),
     (1, (4, 6, 8), 32, 0, 48),
     (1, (4, 6, 8), 48, 0, 64),
