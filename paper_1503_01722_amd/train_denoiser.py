@@ -1,6 +1,9 @@
 """Train and evaluate the learned denoiser on engine-generated pairs.
 
 Usage: python -m paper_1503_01722_amd.train_denoiser --pairs 2000 --train 1800 --out DIR
+Evaluation of stored weights on the held-out pairs only:
+       python -m paper_1503_01722_amd.train_denoiser --first 1800 --pairs 200 --train 0 \
+           --init weights.npy --out DIR
 
 Dataset (pair i, see workloads.denoiser_pair): a CT-like phantom (seed 1000 +
 i), a 6 MV or 15 MeV beam, a low-history run (default 1e6 histories) and a
@@ -71,6 +74,8 @@ def make_pairs(omc, W, ids, shape, h, n_lo, n_hi, params):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=2000)
+    ap.add_argument("--first", type=int, default=0, help="id of the first pair (ids first .. "
+                    "first+pairs-1); with --train 0 and --init, evaluation only")
     ap.add_argument("--train", type=int, default=1800)
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--voxel", type=float, default=0.25)
@@ -82,6 +87,10 @@ def main():
     ap.add_argument("--timing-cases", type=int, default=4)
     ap.add_argument("--out", default="denoiser_run")
     ap.add_argument("--init", default="", help="start from these weights (.npy)")
+    ap.add_argument("--graph-depth", type=int, default=0,
+                    help="engine launch mode for every run: 0 host-driven generations, K > 0 "
+                         "the captured K-generation graph (each timed run follows an untimed "
+                         "run of the same size, which captures it)")
     args = ap.parse_args()
 
     import torch
@@ -90,9 +99,10 @@ def main():
     os.makedirs(args.out, exist_ok=True)
     shape = (args.size,) * 3
     h = args.voxel
-    params = {"graph_depth": 0, "blocks_per_cu": 8}
+    params = {"graph_depth": args.graph_depth, "blocks_per_cu": 8}
     t0 = time.perf_counter()
-    data = make_pairs(omc, W, range(args.pairs), shape, h, args.n_low, args.n_high, params)
+    data = make_pairs(omc, W, range(args.first, args.first + args.pairs), shape, h, args.n_low,
+                      args.n_high, params)
     t_data = time.perf_counter() - t0
     train, test = data[:args.train], data[args.train:][:args.eval]
 
@@ -165,6 +175,8 @@ def main():
         buf2 = torch.zeros_like(buf)
 
         def plain(n, seed):
+            if args.graph_depth > 0:  # capture outside the timed run
+                eng.run_device(n, seed + 1, 0, buf, buf2)
             torch.cuda.synchronize()
             ta = time.perf_counter()
             eng.run_device(n, seed, 0, buf, buf2)
@@ -200,7 +212,7 @@ def main():
                        "t_low_plus_inference_s": t_dn, "n_plain_equal_gamma": n_eq,
                        "t_plain_equal_gamma_s": t_eq})
         log("[timing]", json.dumps(timing[-1]))
-    res = {"pairs": args.pairs, "train": len(train), "eval": len(test), "shape": shape,
+    res = {"pairs": args.pairs, "first": args.first, "train": len(train), "eval": len(test), "shape": shape,
            "voxel_cm": h, "n_low": args.n_low, "n_high": args.n_high, "steps": steps,
            "ms_per_train_step": ms_step, "t_data_s": t_data, "t_train_s": t_train,
            "ms_inference": 1e3 * float(np.median(t_inf)) if t_inf else None,
