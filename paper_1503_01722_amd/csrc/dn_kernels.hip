@@ -476,6 +476,153 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradParams p)
     if (do_bias && int(threadIdx.x) < p.cout && bsum != 0.f) atomicAdd(p.gb + threadIdx.x, bsum);
 }
 
+// ------------------------------------------------ 3x3x3 weight gradient, LDS tile
+// dW[t][ci][co] = sum over output voxels v of X[v + tap t][ci] G[v][co], as
+// matrix products with the voxels as the reduction: a lane's 8 reduction
+// elements are 8 consecutive voxels along x of one channel, so both operands
+// are staged channel-major. A work-group loops over output blocks of 2 x 4 x
+// 16 voxels; per block it stages the output gradient G ([co][z][y][x]) and
+// the input with its halo as three copies shifted by dx = 0, 1, 2 along x
+// ([dx][ci][z][y][x], 16 voxels per row) so that every tap reads 16-byte
+// aligned rows; channel pitches are an odd number of 16-byte chunks. Wave w
+// accumulates taps w, w+4, ... for all (ci, co) tiles over all its blocks and
+// adds them to gw with FP32 atomics at the end; the bias gradient is summed
+// from the staged G. One tap's reduction over a block is 4 products of 32
+// voxels (two rows of 16 each).
+constexpr int kWBZ = 2, kWBY = 4;  // output block (x: 16)
+constexpr int kWRowsX = (kWBZ + 2) * (kWBY + 2);
+constexpr int kWXPitch = kWRowsX * 16 + 8;  // per input channel, BF16 (odd 16-byte chunks)
+constexpr int kWGPitch = kWBZ * kWBY * 16 + 8;
+constexpr int kWTaps = 7;  // taps per wave: ceil(27 / 4)
+
+template <int TI, int TJ>
+__host__ __device__ constexpr size_t wtile_lds_bytes()
+{
+    return (size_t(3) * TI * 16 * kWXPitch + size_t(TJ) * 16 * kWGPitch) * sizeof(uint16_t);
+}
+
+template <int TI, int TJ>
+__global__ void __launch_bounds__(256) wgrad3_tile_kernel(WgradParams p, int nblocks)
+{
+    extern __shared__ __align__(16) uint16_t wl[];
+    uint16_t* xs = wl;                               // [3][TI*16][kWXPitch]
+    uint16_t* gs = wl + 3 * TI * 16 * kWXPitch;      // [TJ*16][kWGPitch]
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int cin = p.c0 + p.c1;
+    const int cg = cin / 8, gg = p.cout / 8;
+    const int nxt = (p.out.nx + 15) / 16, nyt = (p.out.ny + kWBY - 1) / kWBY;
+
+    // input channels cin .. TI*16-1 (the first layer's padding) stay zero
+    for (int i = threadIdx.x; i < 3 * (TI * 16 - cin) * kWXPitch; i += 256) {
+        const int c = cin + (i / kWXPitch) % (TI * 16 - cin);
+        const int d = i / ((TI * 16 - cin) * kWXPitch);
+        xs[(d * TI * 16 + c) * kWXPitch + i % kWXPitch] = 0;
+    }
+    f32x4 acc[kWTaps][TI][TJ];
+#pragma unroll
+    for (int k = 0; k < kWTaps; ++k)
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[k][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+
+    for (int blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const int bx = blk % nxt, by = (blk / nxt) % nyt, bz = blk / (nxt * nyt);
+        const int x0 = bx * 16, y0 = by * kWBY, z0 = bz * kWBZ;
+        __syncthreads();  // the previous block's reads are done
+        // input with halo: piece = (staged voxel, 8 channels) -> the copies it lands in
+        for (int q = threadIdx.x; q < kWRowsX * 18 * cg; q += 256) {
+            const int c = q % cg, v = q / cg;
+            const int lx = v % 18, row = v / 18;
+            const int ly = row % (kWBY + 2), lz = row / (kWBY + 2);
+            const int ix = x0 + lx - 1, iy = y0 + ly - 1, iz = z0 + lz - 1;
+            uint4 raw = {0u, 0u, 0u, 0u};
+            if (ix >= 0 && iy >= 0 && iz >= 0 && ix < p.in.nx && iy < p.in.ny && iz < p.in.nz) {
+                const size_t gv = (size_t(iz) * p.in.ny + iy) * p.in.nx + ix;
+                const int ci = c * 8;
+                const uint16_t* src =
+                    ci < p.c0 ? p.x0 + gv * p.c0 + ci : p.x1 + gv * p.c1 + (ci - p.c0);
+                raw = *reinterpret_cast<const uint4*>(src);
+            }
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&raw);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int xx = lx - d;  // copy d holds staged x' + d at x'
+                if (xx < 0 || xx >= 16) continue;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    xs[(d * TI * 16 + c * 8 + k) * kWXPitch + row * 16 + xx] = e[k];
+            }
+        }
+        // output gradient (zero outside the volume)
+        for (int q = threadIdx.x; q < kWBZ * kWBY * 16 * gg; q += 256) {
+            const int c = q % gg, v = q / gg;
+            const int lx = v % 16, row = v / 16;
+            const int ly = row % kWBY, lz = row / kWBY;
+            const int ox = x0 + lx, oy = y0 + ly, oz = z0 + lz;
+            uint4 raw = {0u, 0u, 0u, 0u};
+            if (ox < p.out.nx && oy < p.out.ny && oz < p.out.nz)
+                raw = *reinterpret_cast<const uint4*>(
+                    p.g + ((size_t(oz) * p.out.ny + oy) * p.out.nx + ox) * p.cout + c * 8);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&raw);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) gs[(c * 8 + k) * kWGPitch + row * 16 + lx] = e[k];
+        }
+        __syncthreads();
+        if (p.gb && int(threadIdx.x) < p.cout)
+            for (int v = 0; v < kWBZ * kWBY * 16; ++v) bsum += bf2f(gs[threadIdx.x * kWGPitch + v]);
+        // four reduction steps of 32 voxels: rows 2kk and 2kk+1, lane group g
+        // takes row 2kk + g/2, voxels 8 (g%2) .. 8 (g%2) + 7
+#pragma unroll
+        for (int kk = 0; kk < kWBZ * kWBY / 2; ++kk) {
+            const int rr = 2 * kk + (g >> 1), xo = 8 * (g & 1);
+            const int zr = rr / kWBY, yr = rr % kWBY;
+            bf16x8 b[TJ];
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+                b[j] = as_bf16x8(*reinterpret_cast<const uint4*>(
+                    gs + (j * 16 + r) * kWGPitch + rr * 16 + xo));
+#pragma unroll
+            for (int k = 0; k < kWTaps; ++k) {
+                const int t = wave + 4 * k;
+                if (t >= 27) break;
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                const int xrow = (zr + dz) * (kWBY + 2) + (yr + dy);
+#pragma unroll
+                for (int i = 0; i < TI; ++i) {
+                    const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4*>(
+                        xs + (dx * TI * 16 + i * 16 + r) * kWXPitch + xrow * 16 + xo));
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j)
+                        acc[k][i][j] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[k][i][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // lane (r, g) holds dW[ci = 16 i + 4 g + e][co = 16 j + r]
+#pragma unroll
+    for (int k = 0; k < kWTaps; ++k) {
+        const int t = wave + 4 * k;
+        if (t >= 27) break;
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ci = i * 16 + 4 * g + e, co = j * 16 + r;
+                    if (ci < p.cin_log && acc[k][i][j][e] != 0.f)
+                        atomicAdd(p.gw + (size_t(t) * p.cin_log + ci) * p.cout + co,
+                                  acc[k][i][j][e]);
+                }
+    }
+    if (p.gb && int(threadIdx.x) < p.cout && bsum != 0.f) atomicAdd(p.gb + threadIdx.x, bsum);
+}
+
 // ------------------------------------------------------------------- packing
 __global__ void __launch_bounds__(256)
 pack_kernel(const float* __restrict__ w, int taps, int cin_log, int cin, int cout, int mode, int K,
@@ -824,6 +971,27 @@ int wgrad_launch(const WgradParams& p, dim3 grid, hipStream_t s)
     return status();
 }
 
+template <int TI, int TJ>
+int wgrad_tile_launch(const WgradParams& p, int cus, hipStream_t s)
+{
+    constexpr size_t lds = wtile_lds_bytes<TI, TJ>();
+    static bool raised = false;  // one attribute call per instantiation
+    if (!raised) {
+        if (hipFuncSetAttribute((const void*)wgrad3_tile_kernel<TI, TJ>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+            return -1;
+        raised = true;
+    }
+    const int nblocks = ((p.out.nx + 15) / 16) * ((p.out.ny + kWBY - 1) / kWBY) *
+                        ((p.out.nz + kWBZ - 1) / kWBZ);
+    if (nblocks == 0) return 0;
+    int grid = 2 * cus;
+    if (grid > nblocks) grid = nblocks;
+    hipLaunchKernelGGL((wgrad3_tile_kernel<TI, TJ>), dim3(unsigned(grid)), dim3(256), lds, s, p,
+                       nblocks);
+    return status();
+}
+
 // the (input tiles, output tiles) shapes of the network's layers
 template <int GEOM>
 int wgrad_geom(const WgradParams& p, int ti, int tj, dim3 grid, hipStream_t s)
@@ -921,6 +1089,20 @@ int launch_conv_wgrad(int geometry, const uint16_t* x0, int c0, const uint16_t* 
     const dim3 grid{unsigned(blocks_x), unsigned(taps), 1u};
     const int ti = (c0 + c1 + 15) / 16, tj = cout / 16;
     hipStream_t s = (hipStream_t)stream;
+    if (geometry == G_CONV3 && in.nz == out.nz && in.ny == out.ny && in.nx == out.nx) {
+        static int cus = 0;
+        if (!cus) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                    hipSuccess)
+                return -1;
+        }
+        // the staged-block kernel for the shapes it is built for
+        if (ti == 1 && tj == 1) return wgrad_tile_launch<1, 1>(p, cus, s);
+        if (ti == 2 && tj == 1) return wgrad_tile_launch<2, 1>(p, cus, s);
+        if (ti == 2 && tj == 2) return wgrad_tile_launch<2, 2>(p, cus, s);
+    }
     switch (geometry) {
     case G_CONV3: return wgrad_geom<G_CONV3>(p, ti, tj, grid, s);
     case G_DOWN: return wgrad_geom<G_DOWN>(p, ti, tj, grid, s);
