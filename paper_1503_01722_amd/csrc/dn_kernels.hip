@@ -750,43 +750,85 @@ loss_grad_kernel(const float* __restrict__ y, const float* __restrict__ target, 
     gy[v] = 2.f * w * (y[v] - t) / sums[1];
 }
 
+// Four threads per voxel, each with 4 of the 16 channels: the 8-byte read of
+// dec and the 16-byte write of gdec of consecutive threads are contiguous.
 __global__ void __launch_bounds__(256)
 head_bwd_kernel(const uint16_t* __restrict__ dec, const float* __restrict__ gy,
                 const float* __restrict__ wh, size_t n, float* __restrict__ gwh,
                 float* __restrict__ gbh, float* __restrict__ gdec)
 {
-    __shared__ float s_w[4];
-    float acc[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = 0.f;
-    float sb = 0.f;
-    for (size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-         v += size_t(gridDim.x) * blockDim.x) {
+    __shared__ float s_c[4][16];
+    __shared__ float s_b[4];
+    const int q = threadIdx.x & 3;  // channels 4q .. 4q+3
+    const float4 w = float4{wh[4 * q], wh[4 * q + 1], wh[4 * q + 2], wh[4 * q + 3]};
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, sb = 0.f;
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < 4 * n;
+         i += size_t(gridDim.x) * blockDim.x) {
+        const size_t v = i >> 2;
         const float gv = gy[v];
-        sb += gv;
-        const uint16_t* d = dec + v * 16;
+        if (q == 0) sb += gv;
+        const uint2 d = reinterpret_cast<const uint2*>(dec)[i];
+        a0 += gv * bf2f(uint16_t(d.x & 0xffffu));
+        a1 += gv * bf2f(uint16_t(d.x >> 16));
+        a2 += gv * bf2f(uint16_t(d.y & 0xffffu));
+        a3 += gv * bf2f(uint16_t(d.y >> 16));
+        reinterpret_cast<float4*>(gdec)[i] = float4{gv * w.x, gv * w.y, gv * w.z, gv * w.w};
+    }
+    // sum over the lanes of the same channel quarter, then over the waves
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            acc[c] += gv * bf2f(d[c]);
-            gdec[v * 16 + c] = gv * wh[c];
-        }
+    for (int off = 4; off < 64; off <<= 1) {
+        a0 += __shfl_xor(a0, off);
+        a1 += __shfl_xor(a1, off);
+        a2 += __shfl_xor(a2, off);
+        a3 += __shfl_xor(a3, off);
     }
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const float s = block_sum(acc[c], s_w);
-        if (threadIdx.x == 0) atomicAdd(gwh + c, s);
+    for (int off = 1; off < 64; off <<= 1) sb += __shfl_xor(sb, off);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) < 4) {
+        s_c[wv][4 * q + 0] = a0;
+        s_c[wv][4 * q + 1] = a1;
+        s_c[wv][4 * q + 2] = a2;
+        s_c[wv][4 * q + 3] = a3;
     }
-    const float s = block_sum(sb, s_w);
-    if (threadIdx.x == 0) atomicAdd(gbh, s);
+    if ((threadIdx.x & 63) == 0) s_b[wv] = sb;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float t = 0.f;
+        for (int k = 0; k < int(blockDim.x >> 6); ++k) t += s_c[k][threadIdx.x];
+        atomicAdd(gwh + threadIdx.x, t);
+    } else if (threadIdx.x == 16) {
+        float t = 0.f;
+        for (int k = 0; k < int(blockDim.x >> 6); ++k) t += s_b[k];
+        atomicAdd(gbh, t);
+    }
 }
 
+// Eight elements per thread (n is a multiple of 8: channels come in eights).
 __global__ void __launch_bounds__(256)
-relu_bwd_kernel(const float* __restrict__ g, const uint16_t* __restrict__ act, size_t n,
+relu_bwd_kernel(const float* __restrict__ g, const uint16_t* __restrict__ act, size_t n8,
                 uint16_t* __restrict__ out)
 {
     const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    out[i] = (act[i] & 0x7fffu) != 0u && !(act[i] & 0x8000u) ? f2bf(g[i]) : uint16_t(0);
+    if (i >= n8) return;
+    const uint4 a = reinterpret_cast<const uint4*>(act)[i];
+    const float4 g0 = reinterpret_cast<const float4*>(g)[2 * i];
+    const float4 g1 = reinterpret_cast<const float4*>(g)[2 * i + 1];
+    const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+    const float gf[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t b = (aw[k] >> (16 * h)) & 0xffffu;
+            const uint32_t y = (b & 0x7fffu) != 0u && !(b & 0x8000u) ? f2bf(gf[2 * k + h]) : 0u;
+            r |= y << (16 * h);
+        }
+        o[k] = r;
+    }
+    reinterpret_cast<uint4*>(out)[i] = uint4{o[0], o[1], o[2], o[3]};
 }
 
 __global__ void __launch_bounds__(256)
@@ -1144,15 +1186,16 @@ int launch_loss(const float* y, const float* target, float inv_dmax, size_t n, f
 int launch_head_bwd(const uint16_t* dec, const float* gy, const float* wh, size_t n, float* gwh,
                     float* gbh, float* gdec, void* stream)
 {
-    hipLaunchKernelGGL(head_bwd_kernel, dim3(grid_strided(n)), dim3(256), 0, (hipStream_t)stream,
-                       dec, gy, wh, n, gwh, gbh, gdec);
+    hipLaunchKernelGGL(head_bwd_kernel, dim3(grid_strided(4 * n)), dim3(256), 0,
+                       (hipStream_t)stream, dec, gy, wh, n, gwh, gbh, gdec);
     return status();
 }
 
 int launch_relu_bwd(const float* g, const uint16_t* act, size_t n, uint16_t* out, void* stream)
 {
-    hipLaunchKernelGGL(relu_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, g,
-                       act, n, out);
+    if (n % 8) return -1;
+    hipLaunchKernelGGL(relu_bwd_kernel, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)stream,
+                       g, act, n / 8, out);
     return status();
 }
 
