@@ -488,7 +488,9 @@ __global__ void __launch_bounds__(256) wgrad_kernel(WgradParams p)
 // accumulates taps w, w+4, ... for all (ci, co) tiles over all its blocks and
 // adds them to gw with FP32 atomics at the end; the bias gradient is summed
 // from the staged G. One tap's reduction over a block is 4 products of 32
-// voxels (two rows of 16 each).
+// voxels (two rows of 16 each). Work-group row blockIdx.y takes input
+// channels 16 TI blockIdx.y .. 16 TI (blockIdx.y + 1) - 1, so that wide
+// layers split their input channels over the grid instead of the LDS.
 constexpr int kWBZ = 2, kWBY = 4;  // output block (x: 16)
 constexpr int kWRowsX = (kWBZ + 2) * (kWBY + 2);
 constexpr int kWXPitch = kWRowsX * 16 + 8;  // per input channel, BF16 (odd 16-byte chunks)
@@ -510,11 +512,12 @@ __global__ void __launch_bounds__(256) wgrad3_tile_kernel(WgradParams p, int nbl
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
-    const int cin = p.c0 + p.c1;
+    const int ci0 = int(blockIdx.y) * TI * 16;  // first input channel of this row
+    const int cin = min(TI * 16, p.c0 + p.c1 - ci0);  // staged here, a multiple of 8
     const int cg = cin / 8, gg = p.cout / 8;
     const int nxt = (p.out.nx + 15) / 16, nyt = (p.out.ny + kWBY - 1) / kWBY;
 
-    // input channels cin .. TI*16-1 (the first layer's padding) stay zero
+    // staged channels cin .. TI*16-1 (past the input's last) stay zero
     for (int i = threadIdx.x; i < 3 * (TI * 16 - cin) * kWXPitch; i += 256) {
         const int c = cin + (i / kWXPitch) % (TI * 16 - cin);
         const int d = i / ((TI * 16 - cin) * kWXPitch);
@@ -542,7 +545,7 @@ __global__ void __launch_bounds__(256) wgrad3_tile_kernel(WgradParams p, int nbl
             uint4 raw = {0u, 0u, 0u, 0u};
             if (ix >= 0 && iy >= 0 && iz >= 0 && ix < p.in.nx && iy < p.in.ny && iz < p.in.nz) {
                 const size_t gv = (size_t(iz) * p.in.ny + iy) * p.in.nx + ix;
-                const int ci = c * 8;
+                const int ci = ci0 + c * 8;
                 const uint16_t* src =
                     ci < p.c0 ? p.x0 + gv * p.c0 + ci : p.x1 + gv * p.c1 + (ci - p.c0);
                 raw = *reinterpret_cast<const uint4*>(src);
@@ -572,7 +575,7 @@ __global__ void __launch_bounds__(256) wgrad3_tile_kernel(WgradParams p, int nbl
             for (int k = 0; k < 8; ++k) gs[(c * 8 + k) * kWGPitch + row * 16 + lx] = e[k];
         }
         __syncthreads();
-        if (p.gb && int(threadIdx.x) < p.cout)
+        if (p.gb && blockIdx.y == 0 && int(threadIdx.x) < p.cout)
             for (int v = 0; v < kWBZ * kWBY * 16; ++v) bsum += bf2f(gs[threadIdx.x * kWGPitch + v]);
         // four reduction steps of 32 voxels: rows 2kk and 2kk+1, lane group g
         // takes row 2kk + g/2, voxels 8 (g%2) .. 8 (g%2) + 7
@@ -614,13 +617,14 @@ __global__ void __launch_bounds__(256) wgrad3_tile_kernel(WgradParams p, int nbl
             for (int j = 0; j < TJ; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int ci = i * 16 + 4 * g + e, co = j * 16 + r;
+                    const int ci = ci0 + i * 16 + 4 * g + e, co = j * 16 + r;
                     if (ci < p.cin_log && acc[k][i][j][e] != 0.f)
                         atomicAdd(p.gw + (size_t(t) * p.cin_log + ci) * p.cout + co,
                                   acc[k][i][j][e]);
                 }
     }
-    if (p.gb && int(threadIdx.x) < p.cout && bsum != 0.f) atomicAdd(p.gb + threadIdx.x, bsum);
+    if (p.gb && blockIdx.y == 0 && int(threadIdx.x) < p.cout && bsum != 0.f)
+        atomicAdd(p.gb + threadIdx.x, bsum);
 }
 
 // ------------------------------------------------------------------- packing
@@ -706,14 +710,20 @@ __device__ __forceinline__ float block_sum(float x, float* s_w)
 __global__ void __launch_bounds__(256)
 max_kernel(const float* __restrict__ a, float scale, size_t n, float* __restrict__ out)
 {
+    __shared__ float s_m[4];
     float m = 0.f;
     for (size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
          v += size_t(gridDim.x) * blockDim.x)
         m = fmaxf(m, a[v] * scale);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0 && m > 0.f)
-        atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    // one atomic per work-group (non-negative floats order as their bit patterns)
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < int(blockDim.x >> 6); ++w) m = fmaxf(m, s_m[w]);
+        if (m > 0.f) atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(m));
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -905,6 +915,12 @@ __global__ void copy_max_kernel(const float* m, double* acc)
 }
 
 unsigned grid_for(size_t n) { return unsigned((n + 255) / 256); }
+// reductions that end in one atomic per work-group on a single address
+unsigned grid_reduce(size_t n)
+{
+    const size_t g = (n + 255) / 256;
+    return unsigned(g < 512 ? (g ? g : 1) : 512);
+}
 unsigned grid_strided(size_t n)
 {
     const size_t g = (n + 255) / 256;
@@ -1014,7 +1030,7 @@ int wgrad_launch(const WgradParams& p, dim3 grid, hipStream_t s)
 }
 
 template <int TI, int TJ>
-int wgrad_tile_launch(const WgradParams& p, int cus, hipStream_t s)
+int wgrad_tile_launch(const WgradParams& p, int ci_rows, int cus, hipStream_t s)
 {
     constexpr size_t lds = wtile_lds_bytes<TI, TJ>();
     static bool raised = false;  // one attribute call per instantiation
@@ -1029,8 +1045,8 @@ int wgrad_tile_launch(const WgradParams& p, int cus, hipStream_t s)
     if (nblocks == 0) return 0;
     int grid = 2 * cus;
     if (grid > nblocks) grid = nblocks;
-    hipLaunchKernelGGL((wgrad3_tile_kernel<TI, TJ>), dim3(unsigned(grid)), dim3(256), lds, s, p,
-                       nblocks);
+    hipLaunchKernelGGL((wgrad3_tile_kernel<TI, TJ>), dim3(unsigned(grid), unsigned(ci_rows)),
+                       dim3(256), lds, s, p, nblocks);
     return status();
 }
 
@@ -1140,10 +1156,14 @@ int launch_conv_wgrad(int geometry, const uint16_t* x0, int c0, const uint16_t* 
                     hipSuccess)
                 return -1;
         }
-        // the staged-block kernel for the shapes it is built for
-        if (ti == 1 && tj == 1) return wgrad_tile_launch<1, 1>(p, cus, s);
-        if (ti == 2 && tj == 1) return wgrad_tile_launch<2, 1>(p, cus, s);
-        if (ti == 2 && tj == 2) return wgrad_tile_launch<2, 2>(p, cus, s);
+        // the staged-block kernel for the network's shapes: (input tiles per
+        // work-group, output tiles), input tiles beyond split over grid rows
+        if (tj == 1 && ti <= 2) return ti == 1 ? wgrad_tile_launch<1, 1>(p, 1, cus, s)
+                                               : wgrad_tile_launch<2, 1>(p, 1, cus, s);
+        if (tj == 2 && ti % 2 == 0) return wgrad_tile_launch<2, 2>(p, ti / 2, cus, s);
+        if (tj == 3 && ti % 2 == 0) return wgrad_tile_launch<2, 3>(p, ti / 2, cus, s);
+        if (tj == 3) return wgrad_tile_launch<1, 3>(p, ti, cus, s);
+        if (tj == 4) return wgrad_tile_launch<1, 4>(p, ti, cus, s);
     }
     switch (geometry) {
     case G_CONV3: return wgrad_geom<G_CONV3>(p, ti, tj, grid, s);
@@ -1173,7 +1193,7 @@ int launch_loss(const float* y, const float* target, float inv_dmax, size_t n, f
                 float* gy, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(max_kernel, dim3(grid_strided(n)), dim3(256), 0, s, target, inv_dmax, n,
+    hipLaunchKernelGGL(max_kernel, dim3(grid_reduce(n)), dim3(256), 0, s, target, inv_dmax, n,
                        sums);
     hipLaunchKernelGGL(loss_sum_kernel, dim3(grid_strided(n)), dim3(256), 0, s, y, target,
                        inv_dmax, n, sums);
@@ -1227,7 +1247,7 @@ int launch_dn_error(const float* dn, const float* lo, const float* sigma, size_t
     // acc[4] (as float) holds the running maximum of lo
     hipStream_t s = (hipStream_t)stream;
     float* lmax = reinterpret_cast<float*>(acc + 4);
-    hipLaunchKernelGGL(max_kernel, dim3(grid_strided(n)), dim3(256), 0, s, lo, 1.0f, n, lmax);
+    hipLaunchKernelGGL(max_kernel, dim3(grid_reduce(n)), dim3(256), 0, s, lo, 1.0f, n, lmax);
     hipLaunchKernelGGL(dn_error_kernel, dim3(grid_strided(n)), dim3(256), 0, s, dn, lo, sigma, n,
                        lmax, acc);
     hipLaunchKernelGGL(copy_max_kernel, dim3(1), dim3(64), 0, s, lmax, acc);
