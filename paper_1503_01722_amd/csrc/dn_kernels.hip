@@ -934,6 +934,17 @@ int conv_launch(const ConvParams& p, dim3 grid, hipStream_t s)
     return status();
 }
 
+// Dynamic LDS above the default 64 KB needs the kernel's limit raised on the
+// current device (a host call, made before each such launch).
+int allow_lds(const void* fn, size_t bytes)
+{
+    if (bytes <= 65536) return 0;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) ==
+                   hipSuccess
+               ? 0
+               : -1;
+}
+
 // Largest LDS block a tile kernel takes (96 channels: one work-group per CU).
 constexpr size_t kTileLdsMax = 96 * 1024;
 
@@ -942,14 +953,7 @@ int tile_launch(const ConvParams& p, int tiles, hipStream_t s)
 {
     using S = TileShape<CIN>;
     static_assert(S::lds <= kTileLdsMax, "staged block within the LDS budget");
-    static bool raised = false;  // one attribute call per instantiation
-    if (!raised) {
-        if (hipFuncSetAttribute((const void*)conv3_tile_kernel<NT, CIN>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                int(kTileLdsMax)) != hipSuccess)
-            return -1;
-        raised = true;
-    }
+    if (allow_lds((const void*)conv3_tile_kernel<NT, CIN>, S::lds)) return -1;
     const unsigned nxt = unsigned((p.out.nx + kTileX - 1) / kTileX);
     const unsigned nyt = unsigned((p.out.ny + S::BY - 1) / S::BY);
     const unsigned nzt = unsigned((p.out.nz + S::BZ - 1) / S::BZ);
@@ -1033,13 +1037,7 @@ template <int TI, int TJ>
 int wgrad_tile_launch(const WgradParams& p, int ci_rows, int cus, hipStream_t s)
 {
     constexpr size_t lds = wtile_lds_bytes<TI, TJ>();
-    static bool raised = false;  // one attribute call per instantiation
-    if (!raised) {
-        if (hipFuncSetAttribute((const void*)wgrad3_tile_kernel<TI, TJ>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
-            return -1;
-        raised = true;
-    }
+    if (allow_lds((const void*)wgrad3_tile_kernel<TI, TJ>, lds)) return -1;
     const int nblocks = ((p.out.nx + 15) / 16) * ((p.out.ny + kWBY - 1) / kWBY) *
                         ((p.out.nz + kWBZ - 1) / kWBZ);
     if (nblocks == 0) return 0;
@@ -1148,14 +1146,10 @@ int launch_conv_wgrad(int geometry, const uint16_t* x0, int c0, const uint16_t* 
     const int ti = (c0 + c1 + 15) / 16, tj = cout / 16;
     hipStream_t s = (hipStream_t)stream;
     if (geometry == G_CONV3 && in.nz == out.nz && in.ny == out.ny && in.nx == out.nx) {
-        static int cus = 0;
-        if (!cus) {
-            int dev = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                    hipSuccess)
-                return -1;
-        }
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return -1;
         // the staged-block kernel for the network's shapes: (input tiles per
         // work-group, output tiles), input tiles beyond split over grid rows
         if (tj == 1 && ti <= 2) return ti == 1 ? wgrad_tile_launch<1, 1>(p, 1, cus, s)
