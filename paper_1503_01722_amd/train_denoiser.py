@@ -37,6 +37,10 @@ def log(*a):
     print(*a, flush=True)
 
 
+def tuned_shape(p):
+    return {k: p[k] for k in ("block_size", "blocks_per_cu", "chunk_histories", "graph_depth")}
+
+
 def make_pairs(omc, W, ids, shape, h, n_lo, n_hi, params):
     import torch
     data = []
@@ -87,6 +91,10 @@ def main():
     ap.add_argument("--timing-cases", type=int, default=4)
     ap.add_argument("--out", default="denoiser_run")
     ap.add_argument("--init", default="", help="start from these weights (.npy)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="in the wall-time comparison, time the low-history run and the plain "
+                         "run of equal gamma each with the launch shape omc_autotune picks for "
+                         "its own history count")
     ap.add_argument("--graph-depth", type=int, default=0,
                     help="engine launch mode for every run: 0 host-driven generations, K > 0 "
                          "the captured K-generation graph (each timed run follows an untimed "
@@ -175,7 +183,7 @@ def main():
         buf2 = torch.zeros_like(buf)
 
         def plain(n, seed):
-            if args.graph_depth > 0:  # capture outside the timed run
+            if eng.get_params()["graph_depth"] > 0:  # capture outside the timed run
                 eng.run_device(n, seed + 1, 0, buf, buf2)
             torch.cuda.synchronize()
             ta = time.perf_counter()
@@ -183,6 +191,9 @@ def main():
             torch.cuda.synchronize()
             return time.perf_counter() - ta, buf.float().reshape(shape)
 
+        shapes = {}
+        if args.autotune:
+            shapes["low"] = tuned_shape(eng.autotune(args.n_low, 5))
         plain(args.n_low, 999)  # warm-up
         t_lo, lo = plain(args.n_low, 7777)
         sig = torch.sqrt(torch.clamp(buf2 / 10 - buf * buf, min=0) / 9).float()
@@ -205,12 +216,14 @@ def main():
                     hi_n = mid
                 else:
                     lo_n = mid
+            if args.autotune:
+                shapes["plain"] = tuned_shape(eng.autotune(hi_n, 6))
             t_eq, _ = plain(hi_n, 4242)
             n_eq = hi_n
         eng.close()
         timing.append({"i": d["i"], "photon": d["photon"], "gamma_dn": p_star,
                        "t_low_plus_inference_s": t_dn, "n_plain_equal_gamma": n_eq,
-                       "t_plain_equal_gamma_s": t_eq})
+                       "t_plain_equal_gamma_s": t_eq, "launch_shapes": shapes})
         log("[timing]", json.dumps(timing[-1]))
     res = {"pairs": args.pairs, "first": args.first, "train": len(train), "eval": len(test), "shape": shape,
            "voxel_cm": h, "n_low": args.n_low, "n_high": args.n_high, "steps": steps,
