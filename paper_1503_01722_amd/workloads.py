@@ -47,6 +47,22 @@ BONE = _material("bone", [("H", 0.034), ("C", 0.155), ("N", 0.042), ("O", 0.435)
 MATERIALS = [WATER, LUNG, BONE]   # material ids 0, 1, 2
 MAT_WATER, MAT_LUNG, MAT_BONE = 0, 1, 2
 
+# Five more ICRU-44-like compositions: with the three above, the library's
+# maximum of eight materials in one phantom (largest LDS tables).
+ADIPOSE = _material("adipose", [("H", 0.114), ("C", 0.598), ("N", 0.007), ("O", 0.278),
+                                ("Na", 0.001), ("S", 0.001), ("Cl", 0.001)], 63.2, 0.95)
+MUSCLE = _material("muscle", [("H", 0.102), ("C", 0.143), ("N", 0.034), ("O", 0.710),
+                              ("Na", 0.001), ("P", 0.002), ("S", 0.003), ("Cl", 0.001),
+                              ("K", 0.004)], 75.3, 1.05)
+CARTILAGE = _material("cartilage", [("H", 0.096), ("C", 0.099), ("N", 0.022), ("O", 0.744),
+                                    ("Na", 0.005), ("P", 0.022), ("S", 0.009), ("Cl", 0.003)],
+                      78.0, 1.10)
+SPONGIOSA = _material("spongiosa", [("H", 0.085), ("C", 0.404), ("N", 0.028), ("O", 0.367),
+                                    ("Na", 0.001), ("Mg", 0.001), ("P", 0.034), ("S", 0.002),
+                                    ("Cl", 0.002), ("K", 0.001), ("Ca", 0.074)], 85.0, 1.18)
+AIR = _material("air", [("C", 0.000124), ("N", 0.755268), ("O", 0.231781)], 85.7, 0.0012)
+MATERIALS_8 = MATERIALS + [ADIPOSE, MUSCLE, CARTILAGE, SPONGIOSA, AIR]
+
 
 def material_from_density(rho):
     """CT-like assignment: rho < 0.5 lung, 0.5 <= rho < 1.2 water, >= 1.2 bone."""
@@ -81,6 +97,17 @@ def layered_phantom(n, h, layers):
         d[sel] = rho
         m[sel] = mid
     return _phantom(d, m, (h, h, h))
+
+
+def eight_material_phantom(n=(40, 16, 16), h=0.5):
+    """Eight slabs along z, one per material of MATERIALS_8 at its nominal
+    density (the maximum number of materials in one phantom)."""
+    nz = n[0]
+    step = nz * h / len(MATERIALS_8)
+    ph = layered_phantom(n, h, [(k * step, (k + 1) * step if k < 7 else nz * h + 1.0, k,
+                                 MATERIALS_8[k]["rho_nom"]) for k in range(len(MATERIALS_8))])
+    ph["materials"] = MATERIALS_8
+    return ph
 
 
 def slab_phantom(n=128, h=0.25):

@@ -69,6 +69,10 @@ def _cases(W):
                     {"kerma_mode": 1})
     out["ragged_7"] = (ph, src, 7, {})
     out["single"] = (ph, src, 1, {})
+    # eight materials: the largest LDS tables (more than 64 KB per work-group)
+    out["eight_materials"] = (W.eight_material_phantom(),
+                              W.photon_beam((4.0, 4.0), (4.0, 4.0), spectrum=W.spectrum_6mv()),
+                              3000, {})
     out["halfslab_small"] = (W.halfslab_phantom(64, 0.5),
                              W.electron_beam(15.0, (10.0, 10.0), (16.0, 16.0), parallel=False),
                              1500, {})
@@ -76,7 +80,7 @@ def _cases(W):
 
 
 CASES = ["water_e15", "slab_6mv", "pair_bone", "gantry_ct", "csda", "kerma", "ragged_7", "single",
-         "halfslab_small"]
+         "halfslab_small", "eight_materials"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -171,6 +175,23 @@ def test_fp32_vs_fp64_build_high_statistics(omc, W, name, n):
         ra, rb = ca[k] / n, cb[k] / n
         report(k, fp32=ra, fp64=rb)
         assert ra == pytest.approx(rb, rel=0.01), k
+
+
+def test_fp32_vs_fp64_eight_materials(omc, W):
+    """The FP32 build with the largest tables (eight materials: more than 64 KB
+    of LDS per work-group) against the FP64 build."""
+    ph = W.eight_material_phantom()
+    src = W.photon_beam((4.0, 4.0), (4.0, 4.0), spectrum=W.spectrum_6mv())
+    n = 2_000_000
+    a, a2, ca = gpu_run(omc, ph, src, n, seed=31)
+    b, b2, cb = gpu_run(omc, ph, src, n, seed=32, parity_fp64=1)
+    ref, _, _ = gpu_run(omc, ph, src, n, seed=33, parity_fp64=1)
+    agr = dose_agreement(a, a2, b, b2, ref)
+    report("eight_materials", **agr)
+    check_fp32_agreement(agr)
+    assert ledger_residual(ca) < 1e-9 and ca["watchdog"] == 0
+    for k in ("ph_flights", "ph_compton", "el_moller", "el_boundary"):
+        assert ca[k] / n == pytest.approx(cb[k] / n, rel=0.01), k
 
 
 def test_fp32_ledger_full_slab(omc, W):
