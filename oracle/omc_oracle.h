@@ -100,6 +100,7 @@ typedef struct {
     int n_batches;
     int kerma_mode;         /* e+- deposited where created */
     int csda_mode;          /* no hinge, no multiple scattering, no hard events */
+    int electron_mode;      /* 0 voxel-limited steps (Sec. 2.1), 1 fixed steps across voxels (Sec. 4) */
 } orc_problem;
 
 /* --- random numbers (Philox4x32-10, Salmon et al. SC'11) ------------------ */

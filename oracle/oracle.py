@@ -74,7 +74,8 @@ class Problem(C.Structure):
                 ("gantry_deg", C.c_double), ("iso_x", C.c_double), ("iso_z", C.c_double),
                 ("Eabs_e", C.c_double), ("Eabs_g", C.c_double), ("Wcc", C.c_double),
                 ("kc", C.c_double), ("dmax_s", C.c_double), ("f_E", C.c_double),
-                ("n_batches", C.c_int), ("kerma_mode", C.c_int), ("csda_mode", C.c_int)]
+                ("n_batches", C.c_int), ("kerma_mode", C.c_int), ("csda_mode", C.c_int),
+                ("electron_mode", C.c_int)]
 
 
 _lib = None
@@ -209,7 +210,7 @@ def node_energies():
 # --- problems ------------------------------------------------------------------------------
 
 DEFAULT_PARAMS = dict(Eabs_e=0.2, Eabs_g=0.05, Wcc=0.05, kc=0.2, dmax_s=0.5, f_E=0.25,
-                      n_batches=10, kerma_mode=0, csda_mode=0)
+                      n_batches=10, kerma_mode=0, csda_mode=0, electron_mode=0)
 
 
 class _ProblemHolder:
@@ -238,7 +239,8 @@ class _ProblemHolder:
             float(source.get("gantry_deg", 0.0)), float(source.get("iso_x", 0.0)),
             float(source.get("iso_z", 0.0)),
             p["Eabs_e"], p["Eabs_g"], p["Wcc"], p["kc"], p["dmax_s"], p["f_E"],
-            int(p["n_batches"]), int(p["kerma_mode"]), int(p["csda_mode"]))
+            int(p["n_batches"]), int(p["kerma_mode"]), int(p["csda_mode"]),
+            int(p["electron_mode"]))
 
 
 def run(phantom, source, n, seed=1, h0=0, params=None, threads=None):

@@ -601,6 +601,128 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
     }
 }
 
+/* --- fixed-step electrons (the gDPM scheme of Sec. 4) --------------------------------
+ *
+ * Sec. 4 contrasts the voxel-limited step above with gDPM's fixed step, in which
+ * an electron crosses voxel faces within a step and only a hard event (or the
+ * other limits) ends it, relying on a scaling of the cross sections between
+ * materials. Reading: a step is planned in mass thickness tau (g/cm^2) with the
+ * mass stopping power, cross sections and transport coefficient of the material
+ * of the voxel where it starts (m0), which stand for every material it crosses:
+ * only the density changes along the step (density scaling). Limits:
+ * tau_maxs = d_maxs x 1 g/cm^3 (a water-equivalent length), tau_maxe and
+ * tau_abs from m0's range table, tau_event = n_mfp / sigma_hat(T0). The path,
+ * with the random hinge at xi tau, is marched voxel by voxel: a voxel of
+ * density rho consumes rho x length of tau, and the CSDA energy lost inside it,
+ * T(R0 - tau_in) - T(R0 - tau_out), is deposited there. A step that leaves the
+ * phantom ends the track (escape). */
+
+/* Move along d until tau_done reaches `target`, depositing the CSDA loss per
+ * voxel. Returns 1 if the particle leaves the phantom. end_abs: the step ends
+ * at the absorption energy exactly. */
+static int march(const ctx_t* C, part_t* p, tally_t* t, const orc_mat_tables* T, double RT,
+                 double target, int end_abs, double* tau_done, double* Tcur)
+{
+    for (;;) {
+        const size_t v = lin(C, p->iv);
+        const double rho = C->rho[v];
+        int ax;
+        const double dface = dist_to_face(C, p->iv, p->x, p->d, &ax);
+        const double rem = target - *tau_done;
+        if (rem <= rho * dface) {
+            const double s = rem / rho;
+            for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + s * p->d[a];
+            const double Tn = end_abs ? C->P->Eabs_e : orc_range_inverse(T->R, RT - target);
+            deposit(t, v, *Tcur - Tn);
+            *Tcur = Tn;
+            *tau_done = target;
+            return 0;
+        }
+        for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + dface * p->d[a];
+        *tau_done = *tau_done + rho * dface;
+        const double Tn = orc_range_inverse(T->R, RT - *tau_done);
+        deposit(t, v, *Tcur - Tn);
+        *Tcur = Tn;
+        /* onto the face, index stepped (as for a voxel-limited crossing) */
+        const int up = p->d[ax] > 0.0;
+        p->x[ax] = up ? (double)(p->iv[ax] + 1) * C->h[ax] : (double)p->iv[ax] * C->h[ax];
+        p->iv[ax] += up ? 1 : -1;
+        t->c.el_boundary++;
+        if (p->iv[ax] < 0 || p->iv[ax] >= C->n[ax]) return 1;
+    }
+}
+
+static void transport_electron_fixed(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
+{
+    const orc_problem* P = C->P;
+    for (;;) {
+        const size_t v = lin(C, p->iv);
+        if (p->E <= P->Eabs_e) {
+            deposit(t, v, p->E);
+            t->c.el_absorbed++;
+            trace_step(C, p, 64);
+            if (p->type == PT_POSITRON) annihilate(C, st, t, &p->rng, p->x, p->iv);
+            return;
+        }
+        const int m0 = P->mat[v];
+        const orc_mat_tables* T = &C->tab[m0];
+        if (!P->csda_mode && p->nmfp < 0.0) p->nmfp = -log(rng_u(&p->rng));
+        const double T0 = p->E;
+        int i;
+        double f;
+        orc__grid_pos(T0, &i, &f);
+        const double RT = lerp(T->R, i, f);
+        const double shm = lerp(T->sigHat, i, f);
+        double t_event = INFINITY;
+        if (!P->csda_mode && shm > 0.0) t_event = p->nmfp / shm;
+        const double t_maxs = P->dmax_s * 1.0; /* g/cm^2: d_maxs of unit density */
+        const double t_maxe = RT - orc_table_lookup(T->R, (1.0 - P->f_E) * T0);
+        const double t_abs = RT - C->Rabs[m0];
+        double tau = t_maxs;
+        int lim = LIM_MAXS;
+        if (t_maxe < tau) { tau = t_maxe; lim = LIM_MAXE; }
+        if (t_abs < tau) { tau = t_abs; lim = LIM_ABS; }
+        if (t_event < tau) { tau = t_event; lim = LIM_EVENT; }
+
+        if (tau > 0.0) {
+            double done = 0.0, Tcur = T0;
+            int out;
+            if (P->csda_mode) {
+                out = march(C, p, t, T, RT, tau, lim == LIM_ABS, &done, &Tcur);
+            } else {
+                const double xi = rng_u(&p->rng);
+                out = march(C, p, t, T, RT, xi * tau, 0, &done, &Tcur);
+                if (!out) {
+                    const double Tplan = orc_range_inverse(T->R, RT - tau);
+                    const double Tmid = 0.5 * (T0 + Tplan);
+                    const double A = orc_ms_screening(C->log2A, tau * orc_table_lookup(T->K1, Tmid));
+                    const double omc = sample_ms(&p->rng, A);
+                    const double phi = 2.0 * PI * rng_u(&p->rng);
+                    orc_rotate(p->d, 1.0 - omc, sqrt(omc * (2.0 - omc)), cos(phi), sin(phi));
+                    out = march(C, p, t, T, RT, tau, lim == LIM_ABS, &done, &Tcur);
+                }
+            }
+            if (!P->csda_mode) {
+                p->nmfp = p->nmfp - shm * done;
+                if (p->nmfp < 0.0) p->nmfp = 0.0;
+            }
+            t->c.el_steps++;
+            p->E = Tcur;
+            if (out) {
+                t->c.E_escaped += p->E;
+                t->c.el_escaped++;
+                trace_step(C, p, 16 + lim + 8);
+                return;
+            }
+        } else if (lim == LIM_ABS) {
+            deposit(t, v, T0 - P->Eabs_e);
+            p->E = P->Eabs_e;
+        }
+        if (lim == LIM_EVENT) hard_event(C, p, T, shm, st, t);
+        trace_step(C, p, 16 + lim);
+    }
+}
+
 /* --- source (Sec. 2.2 "Materials": point source, SSD, field at the surface) --------- */
 
 /* Draws block 0 of stream (seed, h, 0): u1,u2 energy, u3,u4 position.
@@ -693,6 +815,7 @@ static void run_history(const ctx_t* C, uint32_t h, stack_t* st, tally_t* t)
     while (st->n > 0) {
         part_t q = st->a[--st->n];
         if (q.type == PT_PHOTON) transport_photon(C, &q, st, t);
+        else if (C->P->electron_mode == 1) transport_electron_fixed(C, &q, st, t);
         else transport_electron(C, &q, st, t);
     }
 }
