@@ -33,6 +33,10 @@ OPS = {
     "electron": {"el_steps": 380, "el_hard_cand": 114, "el_moller": 230, "el_brems": 230,
                  "pos_annihil": 120},
 }
+# fixed steps across voxels: each face crossed inside a step is a march
+# iteration (distance to the face, range inverse, deposit, index step); with
+# voxel-limited steps a crossing ends a step and is inside el_steps
+OPS_FIXED_CROSSING = {"el_boundary": 70}
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one non-packed lane op per clock
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
@@ -87,7 +91,7 @@ SHAPES = {
 }
 
 
-def cpu_baseline(ph, src, target_s, threads):
+def cpu_baseline(ph, src, target_s, threads, params=None):
     """The FP64 CPU oracle (test infrastructure) on a bounded sample of the same
     workload, as it stands."""
     from oracle import oracle
@@ -97,13 +101,13 @@ def cpu_baseline(ph, src, target_s, threads):
     sizes, times = (20_000, 200_000), []
     for n in sizes:
         t = time.perf_counter()
-        oracle.run(ph, src, n, seed=7, threads=threads)
+        oracle.run(ph, src, n, seed=7, threads=threads, params=params)
         times.append(time.perf_counter() - t)
     per_hist = max((times[1] - times[0]) / (sizes[1] - sizes[0]), 1e-8)
     setup = max(times[0] - sizes[0] * per_hist, 0.0)
     n_sample = int(max(sizes[1], min(1_000_000_000, (target_s - setup) / per_hist)))
     t = time.perf_counter()
-    oracle.run(ph, src, n_sample, seed=7, threads=threads)
+    oracle.run(ph, src, n_sample, seed=7, threads=threads, params=params)
     dt = time.perf_counter() - t
     return {"value": n_sample / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_sample} histories of the same workload (FP64 C oracle, OpenMP), "
@@ -128,11 +132,14 @@ def measured_traffic(kernel):
         return None
 
 
-def roofline_of(kt, units):
+def roofline_of(kt, units, fixed_steps=False):
     """ALU roofline of the dominant transport kernel from per-kernel HIP-event
     times kt and the event counters units of the same steps."""
     dom = max(("photon", "electron"), key=lambda k: kt[k][0])
-    ops = sum(units.get(k, 0) * w for k, w in OPS[dom].items())
+    work = dict(OPS[dom])
+    if fixed_steps and dom == "electron":
+        work.update(OPS_FIXED_CROSSING)
+    ops = sum(units.get(k, 0) * w for k, w in work.items())
     t_dom = kt[dom][0] / 1e3
     launches = max(kt[dom][1], 1)
     achieved = ops / t_dom / 1e12
@@ -226,6 +233,9 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--straggler-lanes", type=int, default=-1)
+    ap.add_argument("--electron-mode", type=int, default=0,
+                    help="0: voxel-limited electron steps (the method); 1: fixed steps "
+                         "across voxels (the gDPM scheme it is compared with)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with omc_autotune before the warm-up")
     ap.add_argument("--no-timing-pass", action="store_true",
@@ -282,6 +292,8 @@ def main():
         shape["block_size"] = args.block_size
     if args.straggler_lanes >= 0:
         shape["straggler_lanes"] = args.straggler_lanes
+    if args.electron_mode:
+        shape["electron_mode"] = args.electron_mode
     eng = omc.Engine(ph)
     eng.set_source(src)
     eng.set_params(parity_fp64=int(args.parity_fp64), **shape)
@@ -330,6 +342,8 @@ def main():
            "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                       "histories_per_step": n, "transport": "fp64" if args.parity_fp64 else "fp32",
                       "tally": "fp64",
+                      "electron_steps": ("fixed, across voxels" if params["electron_mode"]
+                                         else "voxel-limited"),
                       "launch": {k: params[k] for k in ("block_size", "blocks_per_cu",
                                                         "chunk_histories", "graph_depth",
                                                         "queue_factor", "straggler_lanes")}}}
@@ -366,12 +380,13 @@ def main():
         out["events_per_history"] = {k: units[k] / (n * args.steps) for k in
                                      ("ph_flights", "ph_compton", "el_steps", "el_moller",
                                       "set_aside")}
-        out["roofline"] = roofline_of(kt, units)
+        out["roofline"] = roofline_of(kt, units, fixed_steps=args.electron_mode == 1)
     out["max_steps_per_particle"] = c["max_steps"]
     out["watchdog"] = c["watchdog"]
     if not args.no_cpu_baseline and not beamlets:
         threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(ph, src, args.cpu_seconds, threads)
+        out["cpu_baseline"] = cpu_baseline(ph, src, args.cpu_seconds, threads,
+                                           {"electron_mode": args.electron_mode})
     elif not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_beamlets(ph, job, args.cpu_seconds,
                                                     min(16, os.cpu_count() or 1))

@@ -115,6 +115,13 @@ typedef struct {
                                 input is used up and that has at most this many live lanes
                                 left moves them, unchanged, to the next generation of their
                                 type, where they run packed into full waves; 0 = off (16) */
+    int electron_mode;       /* 0: Class II steps limited to one voxel (Sec. 2.1); 1: fixed
+                                steps across voxels, the gDPM scheme Sec. 4 compares with: a
+                                step is planned in mass thickness with the mass tables of the
+                                material where it starts (they stand for every material it
+                                crosses, density scaling only), limited by dmax_s at unit
+                                density, f_E, E_abs and the hard-event mean free path, and
+                                each voxel on its path receives the CSDA loss inside it (0) */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */

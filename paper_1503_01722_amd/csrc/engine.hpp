@@ -214,7 +214,9 @@ struct Launch {
     static int prepare(size_t lds_ph, size_t lds_el);
     static int source(const KernelArgs<R>& a, int grid, int block, void* stream);
     static int photon(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream);
-    static int electron(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream);
+    // fixed: steps across voxels (electron_mode 1), a kernel of its own
+    static int electron(const KernelArgs<R>& a, int grid, int block, size_t lds, bool fixed,
+                        void* stream);
 };
 
 int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,

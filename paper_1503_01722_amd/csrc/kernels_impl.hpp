@@ -30,8 +30,10 @@ int Launch<R>::prepare(size_t lds_ph, size_t lds_el)
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_ph)) != hipSuccess)
         return -1;
     if (lds_el > 65536 &&
-        hipFuncSetAttribute((const void*)electron_kernel<R>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_el)) != hipSuccess)
+        (hipFuncSetAttribute((const void*)electron_kernel<R, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_el)) != hipSuccess ||
+         hipFuncSetAttribute((const void*)electron_kernel<R, true>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_el)) != hipSuccess))
         return -1;
     return 0;
 }
@@ -44,9 +46,15 @@ int Launch<R>::photon(const KernelArgs<R>& a, int grid, int block, size_t lds, v
 }
 
 template <typename R>
-int Launch<R>::electron(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream)
+int Launch<R>::electron(const KernelArgs<R>& a, int grid, int block, size_t lds, bool fixed,
+                        void* stream)
 {
-    hipLaunchKernelGGL(electron_kernel<R>, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
+    if (fixed)
+        hipLaunchKernelGGL((electron_kernel<R, true>), dim3(grid), dim3(block), lds,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL((electron_kernel<R, false>), dim3(grid), dim3(block), lds,
+                           (hipStream_t)stream, a);
     return detail::launch_status();
 }
 

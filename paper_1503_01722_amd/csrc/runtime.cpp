@@ -780,7 +780,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         a.qe_out = Q.q[ec ^ 1];
         a.qp_out = Q.q[pc ^ 1];
         t.begin(2);
-        e = e || omc::Launch<R>::electron(a, tgrid, block, lds_el, st);
+        e = e || omc::Launch<R>::electron(a, tgrid, block, lds_el, P.electron_mode == 1, st);
         t.end();
         return e || omc::launch_queue_reset(c->d_ctrl, (1 << pc) | (1 << ec), st);
     };
@@ -847,7 +847,8 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         std::vector<unsigned char> key(sizeof a + 16 * sizeof(uint64_t));
         const uint64_t shape[16] = {sizeof(R), N,      S,      uint64_t(K), uint64_t(block),
                                     uint64_t(tgrid),   lds_ph, lds_el,      uint64_t(P.timing),
-                                    uint64_t(job.particle), need, 0, 0, 0, 0, 0};
+                                    uint64_t(job.particle), need, uint64_t(P.electron_mode),
+                                    0, 0, 0, 0};
         std::memcpy(key.data(), &a, sizeof a);
         std::memcpy(key.data() + sizeof a, shape, sizeof shape);
         if (!c->graph || key != c->graph_key) {
@@ -1208,6 +1209,7 @@ void omc_default_params(omc_params* p)
     p->beamlet_group = 0;
     p->sparse_threshold = 0.0;
     p->straggler_lanes = 16;
+    p->electron_mode = 0;
 }
 
 int upload_phantom(omc_ctx* c);
@@ -1360,6 +1362,8 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
         return fail(c, OMC_EINVAL, "sparse_threshold must be in [0, 1)");
     if (p->straggler_lanes < 0 || p->straggler_lanes > 63)
         return fail(c, OMC_EINVAL, "straggler_lanes must be in 0..63");
+    if (p->electron_mode != 0 && p->electron_mode != 1)
+        return fail(c, OMC_EINVAL, "electron_mode must be 0 or 1");
     c->prm = *p;
     return OMC_OK;
 }

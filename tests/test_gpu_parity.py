@@ -102,6 +102,44 @@ def test_fp64_parity_counters_identical(omc, orc, W, name):
     np.testing.assert_allclose(d2, od2, rtol=1e-6, atol=1e-9 * scale * scale)
 
 
+FIXED_CASES = ["water_e15", "slab_6mv", "csda", "halfslab_small", "eight_materials", "gantry_ct"]
+
+
+@pytest.mark.parametrize("name", FIXED_CASES)
+def test_fp64_parity_fixed_steps(omc, orc, W, name):
+    """Fixed steps across voxels (electron_mode 1): the FP64 build against the
+    oracle's fixed-step transport, event counters identical."""
+    ph, src, n, params = _cases(W)[name]
+    n = min(n, 5000)
+    params = dict(params, electron_mode=1)
+    print(f"[fp64 parity, fixed steps] {name} n={n} shape={ph['shape']}", flush=True)
+    d, d2, c = gpu_run(omc, ph, src, n, seed=4, h0=1, parity_fp64=1, **params)
+    od, od2, oc = orc.run(ph, src, n, seed=4, h0=1, params=params)
+    report(name, **{k: c[k] for k in ("el_steps", "el_boundary", "ph_flights", "push_el")})
+    mism = {k: (c[k], oc[k]) for k in INT_COUNTERS if c[k] != oc[k]}
+    assert not mism, mism
+    assert ledger_residual(c) < 1e-9 and c["el_hinge_trunc"] == 0
+    scale = max(od.max(), 1e-300)
+    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * scale)
+    np.testing.assert_allclose(d2, od2, rtol=1e-6, atol=1e-9 * scale * scale)
+
+
+@pytest.mark.parametrize("name,n", [("water_e15", 1_000_000), ("halfslab_e15", 2_000_000)])
+def test_fp32_vs_fp64_fixed_steps(omc, W, name, n):
+    """The FP32 fixed-step kernel against the FP64 fixed-step build."""
+    ph, src, _ = W.config(name)
+    print(f"[fp32 vs fp64, fixed steps] {name} n={n}", flush=True)
+    a, a2, ca = gpu_run(omc, ph, src, n, seed=41, electron_mode=1)
+    b, b2, cb = gpu_run(omc, ph, src, n, seed=42, parity_fp64=1, electron_mode=1)
+    ref, _, _ = gpu_run(omc, ph, src, n, seed=43, parity_fp64=1, electron_mode=1)
+    agr = dose_agreement(a, a2, b, b2, ref)
+    report(name, **agr)
+    check_fp32_agreement(agr)
+    assert ledger_residual(ca) < 1e-9 and ca["watchdog"] == 0
+    for k in ("el_steps", "el_moller", "el_boundary"):
+        assert ca[k] / n == pytest.approx(cb[k] / n, rel=0.01), k
+
+
 def test_fp64_parity_chunked_and_split(omc, orc, W):
     """Chunked sources and a split history range change nothing (streams are
     keyed by history): counters identical to the oracle's single run."""
