@@ -64,14 +64,24 @@ typedef struct {
  * uniformly on an fx x fy rectangle centred at (cx, cy) in the plane z = z_field
  * of the gantry-0 frame; a point source sits at (sx, sy, z_field - ssd). The
  * frame is then rotated by gantry_deg about the y axis through (iso_x, iso_z),
- * and the particle enters where the ray from the source first meets the box. */
+ * and the particle enters where the ray from the source first meets the box.
+ *
+ * Phase space (geometry 2; the paper's source interface, Sec. 2.2 "Materials"):
+ * history h takes record h mod n_psf of psf, n_psf x 8 floats per record:
+ * energy (MeV, in (0, 20)), position x, y, z (cm) and direction u, v, w (any
+ * non-zero length; normalised by the library) in the gantry-0 frame, and an
+ * unused eighth float. The gantry rotation applies; the particle moves forward
+ * from its recorded point to where it first meets the box (a record inside the
+ * phantom starts where it is; one whose forward ray misses the box is an
+ * escaped history). Spectrum and field members are ignored. The records are
+ * copied by omc_set_source and omc_run_beamlets. */
 typedef struct {
     int particle;            /* 0 photon, 1 electron */
     int n_bins;              /* spectrum bins; 0 = mono-energetic mono_E */
     const double* edges;     /* n_bins + 1 bin edges, MeV, increasing */
     const double* weights;   /* n_bins non-negative weights (need not be normalised) */
     double mono_E;           /* MeV, used when n_bins == 0 */
-    int geometry;            /* 0 parallel beam along the axis, 1 point source */
+    int geometry;            /* 0 parallel beam along the axis, 1 point source, 2 phase space */
     double ssd;              /* point source to field plane distance, cm */
     double z_field;          /* field plane z in the gantry-0 frame, cm */
     double fx, fy;           /* field size on the field plane, cm */
@@ -79,6 +89,8 @@ typedef struct {
     double sx, sy;           /* focal spot x, y (point source), cm */
     double gantry_deg;       /* rotation about y; 0 = beam along +z */
     double iso_x, iso_z;     /* rotation axis position, cm */
+    int n_psf;               /* phase-space records (geometry 2), 1 .. 2^26 */
+    const float* psf;        /* n_psf x 8 floats (geometry 2), host memory, copied */
 } omc_source;
 
 /* Transport parameters (Sec. 2.1 step limits; Sec. 2.2 "Materials" cut-offs)

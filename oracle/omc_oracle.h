@@ -89,7 +89,7 @@ typedef struct {
     const double* edges;    /* n_bins+1 */
     const double* weights;  /* n_bins */
     double mono_E;
-    int geometry;           /* 0 parallel, 1 point */
+    int geometry;           /* 0 parallel, 1 point, 2 phase space */
     double ssd;             /* source to field plane along the axis */
     double z_field;         /* field plane z in the gantry-0 frame */
     double fx, fy, cx, cy;  /* field size and centre on the field plane */
@@ -101,6 +101,10 @@ typedef struct {
     int kerma_mode;         /* e+- deposited where created */
     int csda_mode;          /* no hinge, no multiple scattering, no hard events */
     int electron_mode;      /* 0 voxel-limited steps (Sec. 2.1), 1 fixed steps across voxels (Sec. 4) */
+    /* phase-space source (geometry 2): history h takes record h mod n_psf of
+     * psf (8 floats: E, x, y, z, u, v, w, unused) */
+    int n_psf;
+    const float* psf;
 } orc_problem;
 
 /* --- random numbers (Philox4x32-10, Salmon et al. SC'11) ------------------ */

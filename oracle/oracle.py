@@ -75,7 +75,7 @@ class Problem(C.Structure):
                 ("Eabs_e", C.c_double), ("Eabs_g", C.c_double), ("Wcc", C.c_double),
                 ("kc", C.c_double), ("dmax_s", C.c_double), ("f_E", C.c_double),
                 ("n_batches", C.c_int), ("kerma_mode", C.c_int), ("csda_mode", C.c_int),
-                ("electron_mode", C.c_int)]
+                ("electron_mode", C.c_int), ("n_psf", C.c_int), ("psf", C.POINTER(C.c_float))]
 
 
 _lib = None
@@ -226,6 +226,9 @@ class _ProblemHolder:
         self.weights = np.ascontiguousarray(source.get("weights", np.zeros(1)), dtype=np.float64)
         nz, ny, nx = phantom["shape"]
         dz, dy, dx = phantom["voxel"]
+        psf = source.get("psf")
+        self.psf = (np.ascontiguousarray(psf, dtype=np.float32).reshape(-1, 8) if psf is not None
+                    else np.zeros((1, 8), np.float32))
         self.struct = Problem(
             nx, ny, nz, dx, dy, dz,
             self.density.ctypes.data_as(C.POINTER(C.c_float)),
@@ -240,7 +243,8 @@ class _ProblemHolder:
             float(source.get("iso_z", 0.0)),
             p["Eabs_e"], p["Eabs_g"], p["Wcc"], p["kc"], p["dmax_s"], p["f_E"],
             int(p["n_batches"]), int(p["kerma_mode"]), int(p["csda_mode"]),
-            int(p["electron_mode"]))
+            int(p["electron_mode"]), int(self.psf.shape[0]) if psf is not None else 0,
+            self.psf.ctypes.data_as(C.POINTER(C.c_float)))
 
 
 def run(phantom, source, n, seed=1, h0=0, params=None, threads=None):

@@ -734,7 +734,7 @@ static int source_particle(const ctx_t* C, uint32_t h, part_t* p)
     rng_init(&r, C->seed, h, 0u, 0u);
     const double u1 = rng_u(&r), u2 = rng_u(&r), u3 = rng_u(&r), u4 = rng_u(&r);
     double E = P->mono_E;
-    if (P->n_bins > 0) {
+    if (P->n_bins > 0 && P->geometry != 2) {
         int b = 0;
         while (b < P->n_bins - 1 && !(C->cdf[b] > u1)) ++b;
         E = P->edges[b] + u2 * (P->edges[b + 1] - P->edges[b]);
@@ -742,7 +742,20 @@ static int source_particle(const ctx_t* C, uint32_t h, part_t* p)
     double X[3] = {P->cx + (u3 - 0.5) * P->fx, P->cy + (u4 - 0.5) * P->fy, P->z_field};
     double d[3] = {0.0, 0.0, 1.0};
     double tS = -INFINITY; /* ray parameter of the source: parallel beams come from afar */
-    if (P->geometry == 1) {
+    if (P->geometry == 2) {
+        /* phase-space record h mod n_psf; the particle moves forward only */
+        const float* rec = P->psf + 8 * (size_t)(h % (uint32_t)P->n_psf);
+        E = (double)rec[0];
+        X[0] = (double)rec[1];
+        X[1] = (double)rec[2];
+        X[2] = (double)rec[3];
+        const double a = (double)rec[4], b = (double)rec[5], c = (double)rec[6];
+        const double nrm = sqrt(a * a + b * b + c * c);
+        d[0] = a / nrm;
+        d[1] = b / nrm;
+        d[2] = c / nrm;
+        tS = 0.0;
+    } else if (P->geometry == 1) {
         const double a = X[0] - P->sx, b = X[1] - P->sy, c = X[2] - (P->z_field - P->ssd);
         const double nrm = sqrt(a * a + b * b + c * c);
         d[0] = a / nrm;

@@ -249,6 +249,49 @@ def photon_beam(field, centre, spectrum=None, mono_E=None, parallel=False, ssd=1
     return src
 
 
+def phase_space(n, particle=0, field=(10.0, 10.0), centre=(16.0, 16.0), ssd=100.0, z_plane=-1.0,
+                spread_deg=1.0, seed=5, stray=0.02):
+    """Synthetic phase-space records (n x 8 float32: E, x, y, z, u, v, w, 0) on
+    the plane z = z_plane above the phantom: rays from a point source at
+    ssd above z = 0 through points uniform on the field, deflected by a normal
+    angle of spread_deg per axis; energies from the 6 MV spectrum (photons) or
+    15 MeV with a 0.3 MeV normal spread (electrons). A fraction stray of the
+    records point away from the phantom (escaped histories)."""
+    rng = np.random.default_rng(seed)
+    fx, fy = field
+    cx, cy = centre
+    px = cx + (rng.random(n) - 0.5) * fx
+    py = cy + (rng.random(n) - 0.5) * fy
+    d = np.stack([px - cx, py - cy, np.full(n, ssd)], axis=1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d[:, :2] += rng.normal(0.0, np.radians(spread_deg), (n, 2))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t = (z_plane - 0.0) / d[:, 2]  # back from z = 0 to the record plane
+    pos = np.stack([px, py, np.zeros(n)], axis=1) + t[:, None] * d
+    away = rng.random(n) < stray
+    d[away, 2] = -d[away, 2]
+    if particle == 0:
+        edges, w = spectrum_6mv()
+        cdf = np.cumsum(w) / np.sum(w)
+        b = np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), len(w) - 1)
+        E = edges[b] + rng.random(n) * (edges[b + 1] - edges[b])
+    else:
+        E = np.clip(15.0 + 0.3 * rng.normal(size=n), 14.0, 16.0)
+    rec = np.zeros((n, 8), np.float32)
+    rec[:, 0] = E
+    rec[:, 1:4] = pos
+    rec[:, 4:7] = d
+    return rec
+
+
+def psf_source(records, particle=0):
+    """A phase-space source (geometry 2) over the given records."""
+    return {"particle": particle, "n_bins": 0, "mono_E": 1.0, "geometry": 2, "ssd": 100.0,
+            "z_field": 0.0, "fx": 1.0, "fy": 1.0, "cx": 0.0, "cy": 0.0, "sx": 0.0, "sy": 0.0,
+            "gantry_deg": 0.0, "iso_x": 0.0, "iso_z": 0.0,
+            "psf": np.ascontiguousarray(records, dtype=np.float32)}
+
+
 def config(name, scale=1.0):
     """The named workload as (phantom, source, n_histories). ``scale`` shrinks the
     history count (for tests) without touching geometry."""
@@ -264,6 +307,11 @@ def config(name, scale=1.0):
         ph = halfslab_phantom(256, 0.2)
         src = electron_beam(15.0, (10.0, 10.0), (25.6, 25.6), parallel=False)
         n = 100_000_000
+    elif name == "slab_6mv_psf":
+        # the bench slab fed from a 2^20-record phase space of the same beam
+        ph = slab_phantom(128, 0.25)
+        src = psf_source(phase_space(1 << 20))
+        n = 10_000_000
     else:
         raise KeyError(name)
     return ph, src, max(1, int(round(n * scale)))

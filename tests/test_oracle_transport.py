@@ -339,3 +339,48 @@ def test_fixed_step_heterogeneous_ledger_and_bookkeeping(orc, W):
     bookkeeping(c, n, 0)
     assert c["el_hinge_trunc"] == 0 and c["el_boundary"] > 0
 
+
+
+# --- phase-space source (geometry 2) ----------------------------------------------------
+
+def test_phase_space_of_one_record_is_a_pencil_beam(orc, W):
+    """Every history taking the same record (position on the entry plane, +z,
+    one energy) is the parallel source with a field of zero size: the same
+    particles on the same streams, so the same counters and dose exactly."""
+    ph = W.water_phantom((30, 12, 12), 0.5)
+    rec = np.zeros((1, 8), np.float32)
+    rec[0, :7] = [12.0, 3.25, 2.75, 0.0, 0.0, 0.0, 1.0]
+    psf = W.psf_source(rec, particle=1)
+    pencil = W.electron_beam(12.0, (0.0, 0.0), (3.25, 2.75), parallel=True)
+    da, _, ca = orc.run(ph, psf, 300, seed=8, threads=2)
+    db, _, cb = orc.run(ph, pencil, 300, seed=8, threads=2)
+    assert {k: ca[k] for k in ca if isinstance(ca[k], int)} == \
+        {k: cb[k] for k in cb if isinstance(cb[k], int)}
+    np.testing.assert_array_equal(da, db)
+
+
+def test_phase_space_records_cycle_and_misses(orc, W):
+    """History h takes record h mod n: a record whose forward ray misses the
+    phantom is an escaped history with its energy; the ledger holds and a
+    record inside the phantom starts where it is."""
+    ph = W.slab_phantom(32, 1.0)
+    rec = np.zeros((3, 8), np.float32)
+    rec[0, :7] = [2.0, 16.0, 16.0, -1.0, 0.0, 0.0, 1.0]    # enters at the top
+    rec[1, :7] = [3.0, 16.0, 16.0, -1.0, 0.0, 0.0, -1.0]   # points away: miss
+    rec[2, :7] = [1.0, 16.0, 16.0, 10.5, 1.0, 0.0, 0.0]    # starts inside, along +x
+    n = 3000
+    _, _, c = orc.run(ph, W.psf_source(rec), n, seed=2, threads=2)
+    assert c["src_miss"] == n // 3
+    assert c["E_incident"] == pytest.approx((2.0 + 3.0 + 1.0) * n / 3, rel=1e-12)
+    assert ledger_ok(c)
+    bookkeeping(c, n - n // 3, 0)
+
+
+def test_phase_space_ledger_6mv(orc, W):
+    ph = W.slab_phantom(64, 0.5)
+    rec = W.phase_space(5000)
+    n = 10_000
+    dose, _, c = orc.run(ph, W.psf_source(rec), n, seed=3, threads=4)
+    assert ledger_ok(c)
+    assert 0 < c["src_miss"] < 0.05 * n
+    bookkeeping(c, n - c["src_miss"], 0)
