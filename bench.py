@@ -44,6 +44,9 @@ WORKLOADS = {
     "slab_6mv": "6 MV photons, 64-bin synthetic spectrum 0.2-6 MeV, 10x10 cm2 at SSD 100 cm, "
                 "128^3 slab of 0.25 cm voxels (water / bone 1.85 / lung 0.26 / water), "
                 "1e7 histories per step",
+    "slab_6mv_psf": "the slab_6mv beam read from a phase space: 2^20 synthetic records (6 MV "
+                    "spectrum, 10x10 cm2 from SSD 100 cm, 1 degree spread, 2 % pointing away) "
+                    "on the plane 1 cm above the 128^3 slab, 1e7 histories per step",
     "water_e15": "15 MeV electrons, 1x1 cm2 parallel beam, 32^3 water of 0.5 cm voxels, "
                  "1e4 histories per step",
     "halfslab_e15": "15 MeV electrons, 10x10 cm2 at SSD 100 cm, 256^3 half-slab of 0.2 cm voxels, "
@@ -86,6 +89,7 @@ def denoiser_flops(n):
 # --autotune flag re-runs it)
 SHAPES = {
     "slab_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
+    "slab_6mv_psf": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
     "water_e15": {"graph_depth": 8, "chunk_histories": 0, "blocks_per_cu": 4},
     "halfslab_e15": {"graph_depth": 6, "chunk_histories": 0, "blocks_per_cu": 8},
 }

@@ -151,6 +151,8 @@ struct BeamSrc {
     int point;               // 1 point source
     int rotate;              // gantry != 0
     uint32_t h0;             // history id of the beam's first history
+    int n_psf;               // phase space: records (history h takes h mod n_psf); 0 = analytic
+    int psf_off;             // first record of this beam's phase space
 };
 
 template <typename R>
@@ -159,6 +161,7 @@ struct SourceView {
     const uint64_t* first;  // [n_beams + 1] prefix sums of the beams' history counts
     const double* cdf;      // per beam n_bins, FP64 running sum normalised by its last entry
     const R* edges;         // per beam n_bins + 1
+    const float* psf;       // phase-space records, 8 floats each
     int n_beams;
     int particle;           // 0 photon, 1 electron (all beams of a run)
     int cell_mode;          // 0: cell = batch of the history; 1: cell = beam index

@@ -75,6 +75,7 @@ struct omc_ctx {
     std::vector<double> rho_max;  // per material
 
     bool has_source = false;
+    std::vector<float> psf;  // phase-space records of the source (geometry 2)
     omc_source src{};
     std::vector<double> edges, weights, cdf;
     omc_params prm{};
@@ -88,6 +89,9 @@ struct omc_ctx {
     char* d_src = nullptr;      // beams, history prefix, spectra of the current job
     size_t src_cap = 0;
     std::vector<char> src_stage;  // host copy of d_src, alive until the run's end
+    float* d_psf = nullptr;     // device copy of psf, uploaded once per omc_set_source
+    size_t psf_cap = 0;         // floats d_psf holds
+    bool psf_dirty = true;
     omc::RunDesc* d_run = nullptr;
     omc::RunDesc* h_run = nullptr;  // pinned
     double* d_dose = nullptr;   // fold target of omc_run
@@ -485,10 +489,11 @@ uint64_t omc_counters::*const kCounterField[omc::kNumCounters] = {
 // Checks a source as omc_set_source documents and returns its spectrum as bin
 // edges and the normalised FP64 running sum of the weights.
 int check_source(const omc_source* s, std::vector<double>& edges, std::vector<double>& cdf,
-                 std::string& why)
+                 std::vector<float>& psf, std::string& why)
 {
     edges.clear();
     cdf.clear();
+    psf.clear();
     if (!s) {
         why = "NULL source";
         return OMC_EINVAL;
@@ -497,9 +502,35 @@ int check_source(const omc_source* s, std::vector<double>& edges, std::vector<do
         why = "particle must be 0 or 1";
         return OMC_EINVAL;
     }
-    if (s->geometry != 0 && s->geometry != 1) {
-        why = "geometry must be 0 or 1";
+    if (s->geometry < 0 || s->geometry > 2) {
+        why = "geometry must be 0, 1 or 2";
         return OMC_EINVAL;
+    }
+    if (s->geometry == 2) {
+        // phase space: records checked and copied; spectrum and field unused
+        if (s->n_psf < 1 || s->n_psf > (1 << 26) || !s->psf) {
+            why = "a phase space needs 1 <= n_psf <= 2^26 records";
+            return OMC_EINVAL;
+        }
+        const double chk[] = {s->gantry_deg, s->iso_x, s->iso_z};
+        for (double v : chk)
+            if (!std::isfinite(v)) {
+                why = "non-finite source geometry";
+                return OMC_EINVAL;
+            }
+        psf.assign(s->psf, s->psf + size_t(s->n_psf) * 8);
+        for (int k = 0; k < s->n_psf; ++k) {
+            const float* r = psf.data() + size_t(k) * 8;
+            bool ok = r[0] > 0.0f && double(r[0]) < omc::kEHi;
+            for (int j = 1; j < 7; ++j) ok = ok && std::isfinite(r[j]);
+            const double n2 = double(r[4]) * r[4] + double(r[5]) * r[5] + double(r[6]) * r[6];
+            if (!ok || !(n2 > 1e-12)) {
+                why = "phase-space record " + std::to_string(k) +
+                      ": energy must be in (0, 20) MeV, position finite, direction non-zero";
+                return OMC_EINVAL;
+            }
+        }
+        return OMC_OK;
     }
     if (!(s->fx > 0) || !(s->fy > 0) || !std::isfinite(s->fx) || !std::isfinite(s->fy)) {
         why = "field size must be > 0";
@@ -556,11 +587,12 @@ int check_source(const omc_source* s, std::vector<double>& edges, std::vector<do
 
 // One beam of a job on the host. Spectra are shared between beams by pointer.
 struct HostBeam {
-    omc_source src;                     // spectrum pointers unused
+    omc_source src;                     // spectrum and record pointers unused
     const std::vector<double>* edges;   // n_bins + 1
     const std::vector<double>* cdf;     // n_bins
     uint64_t n;
     uint32_t h0;
+    const std::vector<float>* psf;      // n_psf x 8 (phase space), else empty
 };
 
 struct Job {
@@ -583,8 +615,14 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
     std::vector<uint64_t> first(nb + 1, 0);
     std::vector<double> cdf;
     std::vector<R> edges;
+    std::vector<float> recs;
     const std::vector<double>* last = nullptr;
-    int last_c = 0, last_e = 0;
+    const std::vector<float>* last_psf = nullptr;
+    int last_c = 0, last_e = 0, last_p = 0;
+    // a run of the context's own source reads the records from their resident
+    // copy (uploaded once per omc_set_source); batched beamlets bring theirs
+    const bool resident = nb == 1 && job.beams[0].src.geometry == 2 &&
+                          job.beams[0].psf == &c->psf;
     for (size_t b = 0; b < nb; ++b) {
         const HostBeam& hb = job.beams[b];
         const omc_source& sr = hb.src;
@@ -604,11 +642,21 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
         o.sg = R(std::sin(gr));
         o.iso_x = R(sr.iso_x);
         o.iso_z = R(sr.iso_z);
-        o.n_bins = sr.n_bins;
+        o.n_bins = sr.geometry == 2 ? 0 : sr.n_bins;
         o.point = sr.geometry == 1;
+        if (sr.geometry == 2) {
+            // beams given the same record array share one device copy
+            if (!resident && hb.psf != last_psf) {
+                last_psf = hb.psf;
+                last_p = int(recs.size() / 8);
+                recs.insert(recs.end(), hb.psf->begin(), hb.psf->end());
+            }
+            o.n_psf = int(hb.psf->size() / 8);
+            o.psf_off = resident ? 0 : last_p;
+        }
         o.rotate = sr.gantry_deg != 0.0;
         o.h0 = hb.h0;
-        if (sr.n_bins > 0) {
+        if (o.n_bins > 0) {
             if (hb.edges != last) {
                 last = hb.edges;
                 last_c = int(cdf.size());
@@ -625,7 +673,8 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
     const size_t o_first = o_beams + align256(nb * sizeof(omc::BeamSrc<R>));
     const size_t o_cdf = o_first + align256((nb + 1) * sizeof(uint64_t));
     const size_t o_edges = o_cdf + align256(std::max<size_t>(cdf.size(), 1) * sizeof(double));
-    const size_t total = o_edges + align256(std::max<size_t>(edges.size(), 1) * sizeof(R));
+    const size_t o_psf = o_edges + align256(std::max<size_t>(edges.size(), 1) * sizeof(R));
+    const size_t total = o_psf + align256(std::max<size_t>(recs.size(), 1) * sizeof(float));
     if (c->src_cap < total) {
         dfree(c->d_src);
         c->src_cap = 0;
@@ -642,11 +691,28 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
     std::memcpy(h + o_first, first.data(), (nb + 1) * sizeof(uint64_t));
     if (!cdf.empty()) std::memcpy(h + o_cdf, cdf.data(), cdf.size() * sizeof(double));
     if (!edges.empty()) std::memcpy(h + o_edges, edges.data(), edges.size() * sizeof(R));
+    if (!recs.empty()) std::memcpy(h + o_psf, recs.data(), recs.size() * sizeof(float));
     HIP_TRY(c, hipMemcpyAsync(c->d_src, h, total, hipMemcpyHostToDevice, s));
+    if (resident && (c->psf_dirty || !c->d_psf)) {
+        if (c->psf_cap < c->psf.size()) {
+            dfree(c->d_psf);
+            c->psf_cap = 0;
+            if (hipMalloc(&c->d_psf, c->psf.size() * sizeof(float)) != hipSuccess) {
+                c->d_psf = nullptr;
+                return fail(c, OMC_ENOMEM, "hipMalloc failed for the phase-space records");
+            }
+            c->psf_cap = c->psf.size();
+        }
+        // c->psf is stable until the next omc_set_source, after this run's end
+        HIP_TRY(c, hipMemcpyAsync(c->d_psf, c->psf.data(), c->psf.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s));
+        c->psf_dirty = false;
+    }
     v.beams = reinterpret_cast<const omc::BeamSrc<R>*>(c->d_src + o_beams);
     v.first = reinterpret_cast<const uint64_t*>(c->d_src + o_first);
     v.cdf = reinterpret_cast<const double*>(c->d_src + o_cdf);
     v.edges = reinterpret_cast<const R*>(c->d_src + o_edges);
+    v.psf = resident ? c->d_psf : reinterpret_cast<const float*>(c->d_src + o_psf);
     v.n_beams = int(nb);
     v.particle = job.particle;
     v.cell_mode = job.cell_mode;
@@ -950,7 +1016,7 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
 {
     const omc_params& P = c->prm;
     Job job;
-    job.beams.push_back(HostBeam{c->src, &c->edges, &c->cdf, N, h0});
+    job.beams.push_back(HostBeam{c->src, &c->edges, &c->cdf, N, h0, &c->psf});
     job.particle = c->src.particle;
     job.cell_mode = 0;
     job.cells = P.n_batches;
@@ -1331,13 +1397,17 @@ int omc_set_source(omc_ctx* c, const omc_source* s)
 {
     if (check_ctx(c) || !s) return fail(c, OMC_EINVAL, "NULL argument");
     std::vector<double> edges, cdf;
+    std::vector<float> psf;
     std::string why;
-    if (check_source(s, edges, cdf, why) != OMC_OK) return fail(c, OMC_EINVAL, why);
+    if (check_source(s, edges, cdf, psf, why) != OMC_OK) return fail(c, OMC_EINVAL, why);
     c->src = *s;
     c->src.edges = nullptr;
     c->src.weights = nullptr;
+    c->src.psf = nullptr;
     c->edges = std::move(edges);
     c->cdf = std::move(cdf);
+    c->psf = std::move(psf);
+    c->psf_dirty = true;
     c->has_source = true;
     return OMC_OK;
 }
@@ -1416,8 +1486,13 @@ int omc_run_beamlets(omc_ctx* c, const omc_beamlet* b, int n_beamlets, uint32_t 
         return fail(c, OMC_EINVAL, "need 1 <= n_beamlets <= 65535");
     // validate every beamlet; spectra given by the same arrays are checked once
     std::vector<std::vector<double>> edges, cdf;
+    std::vector<std::vector<float>> psfs;
     edges.reserve(n_beamlets);
     cdf.reserve(n_beamlets);
+    psfs.reserve(n_beamlets + 1);
+    psfs.emplace_back();  // the empty record list of analytic beamlets
+    const float* last_r = nullptr;
+    int last_nr = -1;
     std::vector<HostBeam> beams(n_beamlets);
     const double* last_e = nullptr;
     const double* last_w = nullptr;
@@ -1430,9 +1505,16 @@ int omc_run_beamlets(omc_ctx* c, const omc_beamlet* b, int n_beamlets, uint32_t 
         if (s.particle != b[0].src.particle)
             return fail(c, OMC_EINVAL, "all beamlets must have the same particle type");
         std::vector<double> e, w;
+        std::vector<float> r;
         std::string why;
-        if (check_source(&s, e, w, why) != OMC_OK)
+        if (check_source(&s, e, w, r, why) != OMC_OK)
             return fail(c, OMC_EINVAL, "beamlet " + std::to_string(i) + ": " + why);
+        // beamlets that pass the same record array share one device copy
+        if (s.geometry == 2 && (s.psf != last_r || s.n_psf != last_nr)) {
+            psfs.push_back(std::move(r));
+            last_r = s.psf;
+            last_nr = s.n_psf;
+        }
         // beamlets that pass the same spectrum arrays share one device copy
         if (edges.empty() || s.n_bins == 0 || s.edges != last_e || s.weights != last_w ||
             s.n_bins != last_n) {
@@ -1445,6 +1527,8 @@ int omc_run_beamlets(omc_ctx* c, const omc_beamlet* b, int n_beamlets, uint32_t 
         beams[i].src = s;
         beams[i].src.edges = nullptr;
         beams[i].src.weights = nullptr;
+        beams[i].src.psf = nullptr;
+        beams[i].psf = s.geometry == 2 ? &psfs.back() : &psfs.front();
         beams[i].edges = &edges.back();
         beams[i].cdf = &cdf.back();
         beams[i].n = b[i].n_histories;
@@ -1695,6 +1779,7 @@ void omc_destroy(omc_ctx* c)
     dfree(c->d_mat);
     dfree(c->d_vox);
     dfree(c->d_src);
+    dfree(c->d_psf);
     dfree(c->d_run);
     dfree(c->d_cscratch);
     dfree(c->d_grid);

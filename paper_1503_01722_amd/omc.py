@@ -51,7 +51,8 @@ class Source(C.Structure):
                 ("geometry", C.c_int), ("ssd", C.c_double), ("z_field", C.c_double),
                 ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
                 ("sx", C.c_double), ("sy", C.c_double), ("gantry_deg", C.c_double),
-                ("iso_x", C.c_double), ("iso_z", C.c_double)]
+                ("iso_x", C.c_double), ("iso_z", C.c_double),
+                ("n_psf", C.c_int), ("psf", C.POINTER(C.c_float))]
 
 
 class Params(C.Structure):
@@ -327,7 +328,8 @@ class Engine:
 
 def _source_struct(src, cache=None):
     """omc_source for a source dict, and the arrays it points into (keep them
-    alive during the call). Equal spectrum arrays share one buffer."""
+    alive during the call). Equal spectrum arrays share one buffer, and so do
+    equal phase-space record arrays."""
     nb = int(src.get("n_bins", 0) or 0)
     key = (id(src.get("edges")), id(src.get("weights")), nb)
     if cache is not None and key in cache:
@@ -337,14 +339,27 @@ def _source_struct(src, cache=None):
         weights = np.ascontiguousarray(src.get("weights", np.zeros(1)), dtype=np.float64)
         if cache is not None:
             cache[key] = (edges, weights)
+    recs = src.get("psf")
+    n_psf = 0
+    psf = None
+    if recs is not None:
+        pkey = ("psf", id(recs))
+        if cache is not None and pkey in cache:
+            psf = cache[pkey]
+        else:
+            psf = np.ascontiguousarray(recs, dtype=np.float32).reshape(-1, 8)
+            if cache is not None:
+                cache[pkey] = psf
+        n_psf = int(psf.shape[0])
     s = Source(int(src["particle"]), nb, _dptr(edges), _dptr(weights),
                float(src.get("mono_E", 0.0)), int(src["geometry"]),
                float(src.get("ssd", 100.0)), float(src.get("z_field", 0.0)),
                float(src["fx"]), float(src["fy"]), float(src["cx"]), float(src["cy"]),
                float(src.get("sx", src["cx"])), float(src.get("sy", src["cy"])),
                float(src.get("gantry_deg", 0.0)), float(src.get("iso_x", 0.0)),
-               float(src.get("iso_z", 0.0)))
-    return s, (edges, weights)
+               float(src.get("iso_z", 0.0)), n_psf,
+               psf.ctypes.data_as(C.POINTER(C.c_float)) if psf is not None else None)
+    return s, (edges, weights, psf)
 
 
 class Sparse:

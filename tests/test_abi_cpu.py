@@ -146,3 +146,32 @@ def test_host_tables_spot_values(omc, W):
     assert t["muC"][i] == pytest.approx(0.0707 * (1 + 0.0), rel=0.02)
     assert np.all(np.diff(t["R"]) > 0) and t["R"][0] == 0.0
     assert np.all(t["sigHat"] == np.maximum.accumulate(t["sigM"] + t["sigB"]))
+
+
+def test_struct_layouts_match_header(omc, tmp_path):
+    """Every ctypes mirror of an include/omc.h struct has the header's size and
+    field offsets (compiled and measured with the host C compiler)."""
+    pairs = {"omc_material": omc.Material, "omc_source": omc.Source, "omc_params": omc.Params,
+             "omc_counters": omc.Counters, "omc_timing": omc.Timing, "omc_beamlet": omc.Beamlet,
+             "omc_sparse_out": omc.SparseOut}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "omc.h"', "int main(void){"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cname, py in pairs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

@@ -1,0 +1,176 @@
+"""GPU tests of the phase-space source (geometry 2: history h starts from record
+h mod n of a list of particles on a plane, Sec. 2.3's alternative to the
+analytic beam), through the C ABI against the FP64 CPU oracle.
+
+* The FP64 parity build reproduces the oracle's integer counters exactly with
+  photon and electron record lists (records cycled, some pointing away from
+  the phantom), under a gantry rotation, with fixed electron steps, and in
+  batched beamlets that mix phase-space and analytic sources.
+* The FP32 build agrees with the FP64 build statistically on the full-size
+  record list, and a record list drawn from the analytic point-source beam
+  gives that beam's dose.
+"""
+import numpy as np
+import pytest
+
+from parity import INT_COUNTERS, dose_agreement, ledger_residual
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def omc():
+    from paper_1503_01722_amd import omc
+    omc.lib()
+    return omc
+
+
+def gpu_run(omc, ph, src, n, seed=1, h0=0, **params):
+    eng = omc.Engine(ph)
+    eng.set_source(src)
+    if params:
+        eng.set_params(**params)
+    d, d2 = eng.run(n, seed=seed, h0=h0)
+    c = eng.counters()
+    eng.close()
+    return d, d2, c
+
+
+def report(tag, **kv):
+    print(tag, " ".join(f"{k}={v}" for k, v in kv.items()), flush=True)
+
+
+def ints(c):
+    return {k: c[k] for k in INT_COUNTERS}
+
+
+def _cases(W):
+    out = {}
+    ph = W.slab_phantom(64, 0.5)
+    out["photons_slab"] = (ph, W.psf_source(W.phase_space(3000, seed=11, stray=0.05)), 7000, {})
+    ph = W.water_phantom((32, 32, 32), 0.5)
+    rec = W.phase_space(1000, particle=1, field=(2.0, 2.0), centre=(8.0, 8.0), seed=12,
+                        stray=0.05)
+    out["electrons_water"] = (ph, W.psf_source(rec, particle=1), 2500, {})
+    out["electrons_fixed"] = (ph, W.psf_source(rec, particle=1), 2500, {"electron_mode": 1})
+    ph = W.ellipsoid_phantom((40, 48, 48), 0.5, n_ell=6, seed=3)
+    src = W.psf_source(W.phase_space(2000, field=(4.0, 4.0), centre=(12.0, 12.0), seed=13))
+    src.update(gantry_deg=30.0, iso_x=12.0, iso_z=10.0)
+    out["photons_gantry"] = (ph, src, 6000, {})
+    out["one_record"] = (W.water_phantom((20, 20, 20), 0.5),
+                         W.psf_source(np.array([[6.0, 5.0, 5.0, -0.5, 0.0, 0.0, 1.0, 0.0]],
+                                               np.float32)), 2000, {})
+    return out
+
+
+CASES = ["photons_slab", "electrons_water", "electrons_fixed", "photons_gantry", "one_record"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fp64_phase_space_counters_identical(omc, orc, W, name):
+    ph, src, n, params = _cases(W)[name]
+    print(f"[fp64 phase space] {name} n={n} records={len(src['psf'])}", flush=True)
+    d, d2, c = gpu_run(omc, ph, src, n, seed=2, h0=5, parity_fp64=1, **params)
+    od, od2, oc = orc.run(ph, src, n, seed=2, h0=5, params=params)
+    report(name, **{k: c[k] for k in ("el_steps", "ph_flights", "push_el", "push_ph")})
+    mism = {k: (c[k], oc[k]) for k in INT_COUNTERS if c[k] != oc[k]}
+    assert not mism, mism
+    assert ledger_residual(c) < 1e-9
+    for k in ("E_incident", "E_deposited", "E_escaped"):
+        assert c[k] == pytest.approx(oc[k], rel=1e-9, abs=1e-9), k
+    scale = max(od.max(), 1e-300)
+    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * scale)
+    np.testing.assert_allclose(d2, od2, rtol=1e-6, atol=1e-9 * scale * scale)
+
+
+def test_fp64_phase_space_graph_mode(omc, orc, W):
+    """Graph mode with chunks carried between generations reads the resident
+    records the same way."""
+    ph, src, n, _ = _cases(W)["photons_slab"]
+    eng = omc.Engine(ph)
+    eng.set_source(src)
+    eng.set_params(parity_fp64=1, graph_depth=2, chunk_histories=1500)
+    eng.run(n, seed=2, h0=5)
+    c = eng.counters()
+    # a second source on the same context replaces the resident records
+    src2 = W.psf_source(W.phase_space(500, seed=21))
+    eng.set_source(src2)
+    eng.run(3000, seed=3)
+    c2 = eng.counters()
+    eng.close()
+    _, _, oc = orc.run(ph, src, n, seed=2, h0=5)
+    _, _, oc2 = orc.run(ph, src2, 3000, seed=3)
+    assert ints(c) == ints(oc)
+    assert ints(c2) == ints(oc2)
+
+
+@pytest.mark.parametrize("depth", [0, 2])
+def test_fp64_beamlets_with_phase_spaces(omc, orc, W, depth):
+    """Batched beamlets mixing analytic sources and two record lists (one
+    shared by two beamlets): every beamlet equals the oracle's run of it alone."""
+    ph = W.ellipsoid_phantom((40, 48, 48), 0.5, n_ell=6, seed=3)
+    ra = W.psf_source(W.phase_space(700, field=(2.0, 2.0), centre=(12.0, 12.0), seed=31))
+    rb = W.psf_source(W.phase_space(300, particle=1, field=(1.0, 1.0), centre=(10.0, 14.0),
+                                    seed=32), particle=1)
+    rg = dict(ra, gantry_deg=90.0, iso_x=12.0, iso_z=10.0)
+    an = W.photon_beam((1.0, 1.0), (12.0, 12.0), spectrum=W.spectrum_6mv())
+    photons = [(ra, 900), (an, 400), (rg, 1200)]
+    h, beams = 0, []
+    for s, n in photons:
+        beams.append((s, n, h))
+        h += n
+    print(f"[fp64 beamlets, phase space] depth={depth}", flush=True)
+    eng = omc.Engine(ph)
+    eng.set_params(parity_fp64=1, graph_depth=depth, chunk_histories=1000 if depth else 0,
+                   queue_factor=8)
+    sp = eng.run_beamlets(beams, seed=6)
+    c = eng.counters()
+    # electrons from a record list in a job of their own
+    spe = eng.run_beamlets([(rb, 600, 0), (rb, 400, 600)], seed=6)
+    ce = eng.counters()
+    eng.close()
+    od, oc = orc.run_beamlets(ph, beams, seed=6)
+    ode, oce = orc.run_beamlets(ph, [(rb, 600, 0), (rb, 400, 600)], seed=6)
+    assert ints(c) == ints(oc)
+    assert ints(ce) == ints(oce)
+    nvox = int(np.prod(ph["shape"]))
+    for s, refs in ((sp, od), (spe, ode)):
+        for b, ref in enumerate(refs):
+            g = s.row(b, nvox).reshape(ph["shape"])
+            scale = max(ref.max(), 1e-300)
+            np.testing.assert_allclose(g, ref, rtol=2e-6, atol=1e-9 * scale)
+
+
+def test_fp32_vs_fp64_phase_space(omc, W):
+    """The bench's phase-space workload (2^20 records of 6 MV on the 128^3
+    slab): the FP32 build against the FP64 build."""
+    ph, src, _ = W.config("slab_6mv_psf")
+    n = 4_000_000
+    print(f"[fp32 vs fp64, phase space] n={n}", flush=True)
+    a, a2, ca = gpu_run(omc, ph, src, n, seed=51)
+    b, b2, cb = gpu_run(omc, ph, src, n, seed=52, parity_fp64=1)
+    ref, _, _ = gpu_run(omc, ph, src, n, seed=53, parity_fp64=1)
+    agr = dose_agreement(a, a2, b, b2, ref)
+    report("slab_6mv_psf", **agr)
+    assert agr["within2s"] > 0.90 and abs(agr["bias"]) < 0.003
+    assert ledger_residual(ca) < 1e-9 and ca["watchdog"] == 0
+    for k in ("ph_flights", "ph_compton", "el_moller", "push_el"):
+        assert ca[k] / n == pytest.approx(cb[k] / n, rel=0.01), k
+
+
+def test_phase_space_of_the_analytic_beam(omc, W):
+    """Records drawn from the analytic 6 MV point-source beam (no angular
+    spread, none pointing away) give the analytic beam's dose."""
+    ph = W.slab_phantom(64, 0.5)
+    field, centre = (6.0, 6.0), (16.0, 16.0)
+    rec = W.phase_space(1 << 20, field=field, centre=centre, spread_deg=0.0, stray=0.0,
+                        seed=61)
+    an = W.photon_beam(field, centre, spectrum=W.spectrum_6mv())
+    n = 1 << 20  # each record once: no latent variance from reused records
+    print(f"[phase space vs analytic beam] n={n}", flush=True)
+    a, a2, _ = gpu_run(omc, ph, W.psf_source(rec), n, seed=62)
+    b, b2, _ = gpu_run(omc, ph, an, n, seed=63)
+    ref, _, _ = gpu_run(omc, ph, an, n, seed=64)
+    agr = dose_agreement(a, a2, b, b2, ref)
+    report("psf_vs_analytic", **agr)
+    assert agr["within2s"] > 0.90 and abs(agr["bias"]) < 0.003
