@@ -73,8 +73,18 @@ typedef struct {
  * unused eighth float. The gantry rotation applies; the particle moves forward
  * from its recorded point to where it first meets the box (a record inside the
  * phantom starts where it is; one whose forward ray misses the box is an
- * escaped history). Spectrum and field members are ignored. The records are
- * copied by omc_set_source and omc_run_beamlets. */
+ * escaped history). Spectrum and field members are ignored.
+ *
+ * The records are host memory (psf_on_device = 0), checked and copied by
+ * omc_set_source and omc_run_beamlets, or device memory (psf_on_device = 1):
+ * particles a caller's own GPU code wrote (the paper's user source function),
+ * read in place. Device records must lie inside one HIP allocation of the
+ * context's device, be complete when the call starts (the check runs on the
+ * null stream) and stay allocated and unchanged until the next omc_set_source
+ * (or, for beamlets, until omc_run_beamlets returns); the library checks them
+ * on the device with the same conditions as host records, and a pointer
+ * outside a device allocation, or an allocation too small for n_psf records,
+ * is rejected with OMC_EINVAL before any kernel reads it. */
 typedef struct {
     int particle;            /* 0 photon, 1 electron */
     int n_bins;              /* spectrum bins; 0 = mono-energetic mono_E */
@@ -90,7 +100,8 @@ typedef struct {
     double gantry_deg;       /* rotation about y; 0 = beam along +z */
     double iso_x, iso_z;     /* rotation axis position, cm */
     int n_psf;               /* phase-space records (geometry 2), 1 .. 2^26 */
-    const float* psf;        /* n_psf x 8 floats (geometry 2), host memory, copied */
+    const float* psf;        /* n_psf x 8 floats (geometry 2) */
+    int psf_on_device;       /* 0: psf is host memory (copied); 1: device memory (read in place) */
 } omc_source;
 
 /* Transport parameters (Sec. 2.1 step limits; Sec. 2.2 "Materials" cut-offs)

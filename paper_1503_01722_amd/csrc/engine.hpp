@@ -152,7 +152,7 @@ struct BeamSrc {
     int rotate;              // gantry != 0
     uint32_t h0;             // history id of the beam's first history
     int n_psf;               // phase space: records (history h takes h mod n_psf); 0 = analytic
-    int psf_off;             // first record of this beam's phase space
+    const float* psf;        // this beam's records, 8 floats each (device memory)
 };
 
 template <typename R>
@@ -161,7 +161,6 @@ struct SourceView {
     const uint64_t* first;  // [n_beams + 1] prefix sums of the beams' history counts
     const double* cdf;      // per beam n_bins, FP64 running sum normalised by its last entry
     const R* edges;         // per beam n_bins + 1
-    const float* psf;       // phase-space records, 8 floats each
     int n_beams;
     int particle;           // 0 photon, 1 electron (all beams of a run)
     int cell_mode;          // 0: cell = batch of the history; 1: cell = beam index
@@ -253,6 +252,10 @@ int launch_scan(const uint32_t* in, uint64_t* out, size_t n, uint64_t* tmp, void
 int launch_compact_write(const double* grid, const float* rho, size_t nvox, int n_beams,
                          const double* scale, const float* thr, const uint64_t* tile_off,
                          uint64_t nnz, uint32_t* voxel, float* dose, void* stream);
+// Phase-space records checked on the device as the host checks its copies:
+// out[0] += 1 and out[1] = min(out[1], k) for every bad record k (energy not in
+// (0, ehi), a non-finite position or direction component, a zero direction).
+int launch_check_records(const float* rec, uint32_t n, double ehi, uint32_t* out, void* stream);
 int launch_philox_debug(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
                         uint32_t* out, void* stream);
 

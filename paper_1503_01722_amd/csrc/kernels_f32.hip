@@ -375,6 +375,30 @@ int launch_stats_reduce(unsigned long long* counters, double* energies, uint32_t
     return detail::launch_status();
 }
 
+__global__ void __launch_bounds__(256)
+check_records_kernel(const float* rec, uint32_t n, double ehi, uint32_t* out)
+{
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= n) return;
+    const float* q = rec + 8 * size_t(k);
+    bool ok = q[0] > 0.0f && double(q[0]) < ehi;
+    for (int j = 1; j < 7; ++j) ok = ok && __builtin_isfinite(q[j]);
+    // float squares are exact in double, so the sum matches the host's
+    const double n2 = double(q[4]) * q[4] + double(q[5]) * q[5] + double(q[6]) * q[6];
+    if (!ok || !(n2 > 1e-12)) {
+        atomicAdd(out, 1u);
+        atomicMin(out + 1, k);
+    }
+}
+
+int launch_check_records(const float* rec, uint32_t n, double ehi, uint32_t* out, void* stream)
+{
+    const unsigned grid = (n + 255) / 256;
+    hipLaunchKernelGGL(check_records_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, rec,
+                       n, ehi, out);
+    return detail::launch_status();
+}
+
 __global__ void philox_debug_kernel(uint32_t seed, uint32_t h, uint32_t qlo, uint32_t qhi,
                                     uint32_t n0, uint32_t nblocks, uint32_t* out)
 {

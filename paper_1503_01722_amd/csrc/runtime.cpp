@@ -90,6 +90,8 @@ struct omc_ctx {
     size_t src_cap = 0;
     std::vector<char> src_stage;  // host copy of d_src, alive until the run's end
     float* d_psf = nullptr;     // device copy of psf, uploaded once per omc_set_source
+    const float* psf_dev = nullptr;  // the caller's device records (psf_on_device), not owned
+    uint32_t* d_chk = nullptr;  // [2] result of the device record check
     size_t psf_cap = 0;         // floats d_psf holds
     bool psf_dirty = true;
     omc::RunDesc* d_run = nullptr;
@@ -488,12 +490,14 @@ uint64_t omc_counters::*const kCounterField[omc::kNumCounters] = {
 // ------------------------------------------------------------------- sources
 // Checks a source as omc_set_source documents and returns its spectrum as bin
 // edges and the normalised FP64 running sum of the weights.
+// Host records are checked and copied into *psf (skipped when psf is null: the
+// caller has them already); device records are checked by check_device_records.
 int check_source(const omc_source* s, std::vector<double>& edges, std::vector<double>& cdf,
-                 std::vector<float>& psf, std::string& why)
+                 std::vector<float>* psf, std::string& why)
 {
     edges.clear();
     cdf.clear();
-    psf.clear();
+    if (psf) psf->clear();
     if (!s) {
         why = "NULL source";
         return OMC_EINVAL;
@@ -518,9 +522,14 @@ int check_source(const omc_source* s, std::vector<double>& edges, std::vector<do
                 why = "non-finite source geometry";
                 return OMC_EINVAL;
             }
-        psf.assign(s->psf, s->psf + size_t(s->n_psf) * 8);
+        if (s->psf_on_device != 0 && s->psf_on_device != 1) {
+            why = "psf_on_device must be 0 or 1";
+            return OMC_EINVAL;
+        }
+        if (s->psf_on_device || !psf) return OMC_OK;
+        psf->assign(s->psf, s->psf + size_t(s->n_psf) * 8);
         for (int k = 0; k < s->n_psf; ++k) {
-            const float* r = psf.data() + size_t(k) * 8;
+            const float* r = psf->data() + size_t(k) * 8;
             bool ok = r[0] > 0.0f && double(r[0]) < omc::kEHi;
             for (int j = 1; j < 7; ++j) ok = ok && std::isfinite(r[j]);
             const double n2 = double(r[4]) * r[4] + double(r[5]) * r[5] + double(r[6]) * r[6];
@@ -586,13 +595,56 @@ int check_source(const omc_source* s, std::vector<double>& edges, std::vector<do
 }
 
 // One beam of a job on the host. Spectra are shared between beams by pointer.
+// Device records (psf_on_device): the pointer must lie in a HIP allocation on the
+// context's device that holds all n records; then every record is checked on
+// the device with the host's conditions, before any kernel reads them.
+int check_device_records(omc_ctx* c, const float* p, int n, std::string& why)
+{
+    hipPointerAttribute_t at{};
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    const size_t bytes = size_t(n) * 8 * sizeof(float);
+    const bool dev = hipPointerGetAttributes(&at, p) == hipSuccess &&
+                     at.type == hipMemoryTypeDevice && at.device == c->device;
+    const bool range =
+        dev && hipMemGetAddressRange(&base, &size, const_cast<float*>(p)) == hipSuccess &&
+        reinterpret_cast<uintptr_t>(p) >= reinterpret_cast<uintptr_t>(base) &&
+        reinterpret_cast<uintptr_t>(p) + bytes <= reinterpret_cast<uintptr_t>(base) + size;
+    (void)hipGetLastError();
+    if (!dev || !range || reinterpret_cast<uintptr_t>(p) % alignof(float)) {
+        why = "psf_on_device: the records must be an allocation of this context's device "
+              "holding n_psf x 8 floats";
+        return OMC_EINVAL;
+    }
+    if (!c->d_chk && hipMalloc(&c->d_chk, 2 * sizeof(uint32_t)) != hipSuccess) {
+        c->d_chk = nullptr;
+        why = "hipMalloc failed for the record check";
+        return OMC_ENOMEM;
+    }
+    uint32_t h[2] = {0u, 0xFFFFFFFFu};
+    if (hipMemcpy(c->d_chk, h, sizeof h, hipMemcpyHostToDevice) != hipSuccess ||
+        omc::launch_check_records(p, uint32_t(n), omc::kEHi, c->d_chk, nullptr) ||
+        hipMemcpy(h, c->d_chk, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        why = "the device record check failed";
+        return OMC_EDEVICE;
+    }
+    if (h[0]) {
+        why = "phase-space record " + std::to_string(h[1]) +
+              ": energy must be in (0, 20) MeV, position finite, direction non-zero";
+        return OMC_EINVAL;
+    }
+    return OMC_OK;
+}
+
 struct HostBeam {
     omc_source src;                     // spectrum and record pointers unused
     const std::vector<double>* edges;   // n_bins + 1
     const std::vector<double>* cdf;     // n_bins
     uint64_t n;
     uint32_t h0;
-    const std::vector<float>* psf;      // n_psf x 8 (phase space), else empty
+    const std::vector<float>* psf;      // n_psf x 8 host records (phase space), else empty
+    const float* psf_dev = nullptr;     // or the caller's device records
 };
 
 struct Job {
@@ -622,7 +674,8 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
     // a run of the context's own source reads the records from their resident
     // copy (uploaded once per omc_set_source); batched beamlets bring theirs
     const bool resident = nb == 1 && job.beams[0].src.geometry == 2 &&
-                          job.beams[0].psf == &c->psf;
+                          !job.beams[0].psf_dev && job.beams[0].psf == &c->psf;
+    std::vector<long long> rec_at(nb, -1);  // first float of a beam's records in recs
     for (size_t b = 0; b < nb; ++b) {
         const HostBeam& hb = job.beams[b];
         const omc_source& sr = hb.src;
@@ -646,13 +699,18 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
         o.point = sr.geometry == 1;
         if (sr.geometry == 2) {
             // beams given the same record array share one device copy
-            if (!resident && hb.psf != last_psf) {
-                last_psf = hb.psf;
-                last_p = int(recs.size() / 8);
-                recs.insert(recs.end(), hb.psf->begin(), hb.psf->end());
+            if (hb.psf_dev) {
+                o.n_psf = sr.n_psf;
+                o.psf = hb.psf_dev;
+            } else {
+                if (!resident && hb.psf != last_psf) {
+                    last_psf = hb.psf;
+                    last_p = int(recs.size() / 8);
+                    recs.insert(recs.end(), hb.psf->begin(), hb.psf->end());
+                }
+                o.n_psf = int(hb.psf->size() / 8);
+                if (!resident) rec_at[b] = 8LL * last_p;
             }
-            o.n_psf = int(hb.psf->size() / 8);
-            o.psf_off = resident ? 0 : last_p;
         }
         o.rotate = sr.gantry_deg != 0.0;
         o.h0 = hb.h0;
@@ -685,14 +743,6 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
         }
         c->src_cap = want;
     }
-    c->src_stage.assign(total, 0);
-    char* h = c->src_stage.data();
-    std::memcpy(h + o_beams, bs.data(), nb * sizeof(omc::BeamSrc<R>));
-    std::memcpy(h + o_first, first.data(), (nb + 1) * sizeof(uint64_t));
-    if (!cdf.empty()) std::memcpy(h + o_cdf, cdf.data(), cdf.size() * sizeof(double));
-    if (!edges.empty()) std::memcpy(h + o_edges, edges.data(), edges.size() * sizeof(R));
-    if (!recs.empty()) std::memcpy(h + o_psf, recs.data(), recs.size() * sizeof(float));
-    HIP_TRY(c, hipMemcpyAsync(c->d_src, h, total, hipMemcpyHostToDevice, s));
     if (resident && (c->psf_dirty || !c->d_psf)) {
         if (c->psf_cap < c->psf.size()) {
             dfree(c->d_psf);
@@ -708,11 +758,23 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
                                   hipMemcpyHostToDevice, s));
         c->psf_dirty = false;
     }
+    // record pointers: the resident copy, or this job's records in d_src
+    for (size_t b = 0; b < nb; ++b)
+        if (bs[b].n_psf > 0 && !job.beams[b].psf_dev)
+            bs[b].psf = rec_at[b] < 0 ? c->d_psf
+                                      : reinterpret_cast<const float*>(c->d_src + o_psf) + rec_at[b];
+    c->src_stage.assign(total, 0);
+    char* h = c->src_stage.data();
+    std::memcpy(h + o_beams, bs.data(), nb * sizeof(omc::BeamSrc<R>));
+    std::memcpy(h + o_first, first.data(), (nb + 1) * sizeof(uint64_t));
+    if (!cdf.empty()) std::memcpy(h + o_cdf, cdf.data(), cdf.size() * sizeof(double));
+    if (!edges.empty()) std::memcpy(h + o_edges, edges.data(), edges.size() * sizeof(R));
+    if (!recs.empty()) std::memcpy(h + o_psf, recs.data(), recs.size() * sizeof(float));
+    HIP_TRY(c, hipMemcpyAsync(c->d_src, h, total, hipMemcpyHostToDevice, s));
     v.beams = reinterpret_cast<const omc::BeamSrc<R>*>(c->d_src + o_beams);
     v.first = reinterpret_cast<const uint64_t*>(c->d_src + o_first);
     v.cdf = reinterpret_cast<const double*>(c->d_src + o_cdf);
     v.edges = reinterpret_cast<const R*>(c->d_src + o_edges);
-    v.psf = resident ? c->d_psf : reinterpret_cast<const float*>(c->d_src + o_psf);
     v.n_beams = int(nb);
     v.particle = job.particle;
     v.cell_mode = job.cell_mode;
@@ -1016,7 +1078,7 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
 {
     const omc_params& P = c->prm;
     Job job;
-    job.beams.push_back(HostBeam{c->src, &c->edges, &c->cdf, N, h0, &c->psf});
+    job.beams.push_back(HostBeam{c->src, &c->edges, &c->cdf, N, h0, &c->psf, c->psf_dev});
     job.particle = c->src.particle;
     job.cell_mode = 0;
     job.cells = P.n_batches;
@@ -1399,7 +1461,14 @@ int omc_set_source(omc_ctx* c, const omc_source* s)
     std::vector<double> edges, cdf;
     std::vector<float> psf;
     std::string why;
-    if (check_source(s, edges, cdf, psf, why) != OMC_OK) return fail(c, OMC_EINVAL, why);
+    if (check_source(s, edges, cdf, &psf, why) != OMC_OK) return fail(c, OMC_EINVAL, why);
+    const bool dev = s->geometry == 2 && s->psf_on_device;
+    if (dev) {
+        HIP_TRY(c, hipSetDevice(c->device));
+        const int rc = check_device_records(c, s->psf, s->n_psf, why);
+        if (rc != OMC_OK) return fail(c, rc, why);
+    }
+    c->psf_dev = dev ? s->psf : nullptr;
     c->src = *s;
     c->src.edges = nullptr;
     c->src.weights = nullptr;
@@ -1492,7 +1561,7 @@ int omc_run_beamlets(omc_ctx* c, const omc_beamlet* b, int n_beamlets, uint32_t 
     psfs.reserve(n_beamlets + 1);
     psfs.emplace_back();  // the empty record list of analytic beamlets
     const float* last_r = nullptr;
-    int last_nr = -1;
+    int last_nr = -1, last_dev = -1;
     std::vector<HostBeam> beams(n_beamlets);
     const double* last_e = nullptr;
     const double* last_w = nullptr;
@@ -1507,13 +1576,22 @@ int omc_run_beamlets(omc_ctx* c, const omc_beamlet* b, int n_beamlets, uint32_t 
         std::vector<double> e, w;
         std::vector<float> r;
         std::string why;
-        if (check_source(&s, e, w, r, why) != OMC_OK)
+        // records given by the same array as the previous beamlet's are checked
+        // and copied once (they share one device copy)
+        const bool new_list = s.geometry == 2 && (s.psf != last_r || s.n_psf != last_nr ||
+                                                  s.psf_on_device != last_dev);
+        if (check_source(&s, e, w, new_list ? &r : nullptr, why) != OMC_OK)
             return fail(c, OMC_EINVAL, "beamlet " + std::to_string(i) + ": " + why);
-        // beamlets that pass the same record array share one device copy
-        if (s.geometry == 2 && (s.psf != last_r || s.n_psf != last_nr)) {
+        if (new_list) {
+            if (s.psf_on_device) {
+                HIP_TRY(c, hipSetDevice(c->device));
+                const int rc = check_device_records(c, s.psf, s.n_psf, why);
+                if (rc != OMC_OK) return fail(c, rc, "beamlet " + std::to_string(i) + ": " + why);
+            }
             psfs.push_back(std::move(r));
             last_r = s.psf;
             last_nr = s.n_psf;
+            last_dev = s.psf_on_device;
         }
         // beamlets that pass the same spectrum arrays share one device copy
         if (edges.empty() || s.n_bins == 0 || s.edges != last_e || s.weights != last_w ||
@@ -1529,6 +1607,7 @@ int omc_run_beamlets(omc_ctx* c, const omc_beamlet* b, int n_beamlets, uint32_t 
         beams[i].src.weights = nullptr;
         beams[i].src.psf = nullptr;
         beams[i].psf = s.geometry == 2 ? &psfs.back() : &psfs.front();
+        beams[i].psf_dev = s.geometry == 2 && s.psf_on_device ? s.psf : nullptr;
         beams[i].edges = &edges.back();
         beams[i].cdf = &cdf.back();
         beams[i].n = b[i].n_histories;
@@ -1780,6 +1859,7 @@ void omc_destroy(omc_ctx* c)
     dfree(c->d_vox);
     dfree(c->d_src);
     dfree(c->d_psf);
+    dfree(c->d_chk);
     dfree(c->d_run);
     dfree(c->d_cscratch);
     dfree(c->d_grid);

@@ -52,7 +52,7 @@ class Source(C.Structure):
                 ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
                 ("sx", C.c_double), ("sy", C.c_double), ("gantry_deg", C.c_double),
                 ("iso_x", C.c_double), ("iso_z", C.c_double),
-                ("n_psf", C.c_int), ("psf", C.POINTER(C.c_float))]
+                ("n_psf", C.c_int), ("psf", C.POINTER(C.c_float)), ("psf_on_device", C.c_int)]
 
 
 class Params(C.Structure):
@@ -244,7 +244,9 @@ class Engine:
     def set_source(self, src):
         s, keep = _source_struct(src)
         _check(lib().omc_set_source(self._h, C.byref(s)), self._h)
-        del keep
+        # device records are read in place by every run: hold them until the
+        # next source replaces them
+        self._device_records = keep[2] if s.psf_on_device else None
 
     def set_params(self, **kw):
         p = Params.from_buffer_copy(self.params)
@@ -342,7 +344,16 @@ def _source_struct(src, cache=None):
     recs = src.get("psf")
     n_psf = 0
     psf = None
-    if recs is not None:
+    on_device = 0
+    if recs is not None and getattr(recs, "is_cuda", False):
+        # records a caller's GPU code wrote (a torch tensor): read in place
+        import torch
+        if recs.dtype != torch.float32 or recs.dim() != 2 or recs.shape[1] != 8 \
+                or not recs.is_contiguous():
+            raise ValueError("device phase-space records must be a contiguous float32 "
+                             "tensor of shape (n, 8)")
+        psf, n_psf, on_device = recs, int(recs.shape[0]), 1
+    elif recs is not None:
         pkey = ("psf", id(recs))
         if cache is not None and pkey in cache:
             psf = cache[pkey]
@@ -358,7 +369,9 @@ def _source_struct(src, cache=None):
                float(src.get("sx", src["cx"])), float(src.get("sy", src["cy"])),
                float(src.get("gantry_deg", 0.0)), float(src.get("iso_x", 0.0)),
                float(src.get("iso_z", 0.0)), n_psf,
-               psf.ctypes.data_as(C.POINTER(C.c_float)) if psf is not None else None)
+               (C.cast(C.c_void_p(psf.data_ptr()), C.POINTER(C.c_float)) if on_device else
+                psf.ctypes.data_as(C.POINTER(C.c_float)) if psf is not None else None),
+               on_device)
     return s, (edges, weights, psf)
 
 

@@ -285,11 +285,13 @@ def phase_space(n, particle=0, field=(10.0, 10.0), centre=(16.0, 16.0), ssd=100.
 
 
 def psf_source(records, particle=0):
-    """A phase-space source (geometry 2) over the given records."""
+    """A phase-space source (geometry 2) over the given records: an (n, 8) array
+    on the host, or a float32 device tensor that GPU code wrote (read in place)."""
+    if not getattr(records, "is_cuda", False):
+        records = np.ascontiguousarray(records, dtype=np.float32)
     return {"particle": particle, "n_bins": 0, "mono_E": 1.0, "geometry": 2, "ssd": 100.0,
             "z_field": 0.0, "fx": 1.0, "fy": 1.0, "cx": 0.0, "cy": 0.0, "sx": 0.0, "sy": 0.0,
-            "gantry_deg": 0.0, "iso_x": 0.0, "iso_z": 0.0,
-            "psf": np.ascontiguousarray(records, dtype=np.float32)}
+            "gantry_deg": 0.0, "iso_x": 0.0, "iso_z": 0.0, "psf": records}
 
 
 def config(name, scale=1.0):

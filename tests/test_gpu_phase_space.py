@@ -174,3 +174,128 @@ def test_phase_space_of_the_analytic_beam(omc, W):
     agr = dose_agreement(a, a2, b, b2, ref)
     report("psf_vs_analytic", **agr)
     assert agr["within2s"] > 0.90 and abs(agr["bias"]) < 0.003
+
+
+# --------------------------------------------- records written by GPU code
+def _device_records(n, seed):
+    """A user source function on the GPU: particles drawn by torch kernels into
+    a (n, 8) float32 device tensor (15 MeV-ish electrons and 6 MeV photons are
+    not mixed: one particle type per source)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    r = torch.zeros((n, 8), dtype=torch.float32, device="cuda")
+    r[:, 0] = 0.5 + 5.5 * torch.rand(n, generator=g, device="cuda")
+    r[:, 1] = 14.0 + 4.0 * torch.rand(n, generator=g, device="cuda")
+    r[:, 2] = 14.0 + 4.0 * torch.rand(n, generator=g, device="cuda")
+    r[:, 3] = -0.5
+    r[:, 4:6] = 0.05 * torch.randn((n, 2), generator=g, device="cuda")
+    r[:, 6] = 1.0
+    r[::41, 6] = -1.0  # some point away from the phantom
+    torch.cuda.synchronize()
+    return r
+
+
+def test_fp64_device_records_parity(omc, orc, W):
+    """Records a caller's GPU code wrote, read in place: counters equal the
+    oracle's run of the same records copied to the host, and the dose equals
+    the host-record path's."""
+    ph = W.slab_phantom(64, 0.5)
+    rec = _device_records(2500, seed=71)
+    host = rec.cpu().numpy()
+    n = 6000
+    print(f"[fp64 device records] n={n} records={len(host)}", flush=True)
+    d, d2, c = gpu_run(omc, ph, W.psf_source(rec), n, seed=7, h0=2, parity_fp64=1)
+    hd, _, hc = gpu_run(omc, ph, W.psf_source(host), n, seed=7, h0=2, parity_fp64=1)
+    od, _, oc = orc.run(ph, W.psf_source(host), n, seed=7, h0=2)
+    report("device_records", **{k: c[k] for k in ("el_steps", "ph_flights", "push_el")})
+    assert ints(c) == ints(oc) and ints(c) == ints(hc)
+    scale = max(od.max(), 1e-300)
+    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * scale)
+    np.testing.assert_allclose(d, hd, rtol=1e-12, atol=1e-15 * scale)
+
+
+def test_device_records_graph_and_beamlets(omc, orc, W):
+    """Device records in graph mode (FP32 against the host-record path, same
+    counters) and in a beamlet job beside host records (FP64 against the
+    oracle)."""
+    ph = W.slab_phantom(64, 0.5)
+    rec = _device_records(4000, seed=72)
+    host = rec.cpu().numpy()
+    runs = []
+    for r in (rec, host):
+        eng = omc.Engine(ph)
+        eng.set_source(W.psf_source(r))
+        eng.set_params(graph_depth=3, chunk_histories=20_000)
+        d, _ = eng.run(100_000, seed=9)
+        runs.append((d, ints(eng.counters())))
+        eng.close()
+    assert runs[0][1] == runs[1][1]
+    np.testing.assert_allclose(runs[0][0], runs[1][0], rtol=1e-5, atol=1e-7 * runs[1][0].max())
+    other = W.psf_source(W.phase_space(600, seed=73))
+    beams = [(W.psf_source(rec), 700, 0), (other, 500, 700), (W.psf_source(rec), 300, 1200)]
+    eng = omc.Engine(ph)
+    eng.set_params(parity_fp64=1)
+    sp = eng.run_beamlets(beams, seed=3)
+    c = eng.counters()
+    eng.close()
+    hbeams = [(W.psf_source(host), 700, 0), (other, 500, 700), (W.psf_source(host), 300, 1200)]
+    od, oc = orc.run_beamlets(ph, hbeams, seed=3)
+    assert ints(c) == ints(oc)
+    nvox = int(np.prod(ph["shape"]))
+    for b, ref in enumerate(od):
+        g = sp.row(b, nvox).reshape(ph["shape"])
+        np.testing.assert_allclose(g, ref, rtol=2e-6, atol=1e-9 * max(ref.max(), 1e-300))
+
+
+def test_device_records_rejected(omc, W):
+    """Bad device records and pointers are refused on the host or by the
+    device check, before any transport kernel reads them; the context keeps
+    its previous source."""
+    import ctypes as C
+    import torch
+    ph = W.water_phantom((20, 20, 20), 0.5)
+    eng = omc.Engine(ph)
+    good = W.psf_source(W.phase_space(100, field=(4.0, 4.0), centre=(5.0, 5.0), seed=74))
+    eng.set_source(good)
+    bad = _device_records(1000, seed=75)
+    bad[17, 0] = 0.0
+    bad[903, 5] = float("nan")
+    with pytest.raises(omc.OmcError) as e:
+        eng.set_source(W.psf_source(bad))
+    assert e.value.code == omc.OMC_EINVAL and "record 17:" in str(e.value)
+    bad[17, 0] = 25.0
+    with pytest.raises(omc.OmcError) as e:
+        eng.set_source(W.psf_source(bad))
+    assert "record 17:" in str(e.value)
+    bad[17, 0] = 1.0
+    with pytest.raises(omc.OmcError) as e:
+        eng.set_source(W.psf_source(bad))
+    assert "record 903:" in str(e.value)
+    bad[903, 4:7] = 0.0
+    with pytest.raises(omc.OmcError) as e:
+        eng.set_source(W.psf_source(bad))
+    assert "record 903:" in str(e.value)
+    L = omc.lib()
+    # more records than the allocation holds: refused by the range check
+    t = _device_records(1000, seed=76)
+    s, keep = omc._source_struct(W.psf_source(t))
+    s.n_psf = 1 << 26
+    assert L.omc_set_source(eng._h, C.byref(s)) == omc.OMC_EINVAL
+    # host memory flagged as device memory: refused by the pointer check
+    host = np.ascontiguousarray(t.cpu().numpy())
+    s.n_psf = 1000
+    s.psf = host.ctypes.data_as(C.POINTER(C.c_float))
+    assert L.omc_set_source(eng._h, C.byref(s)) == omc.OMC_EINVAL
+    s.psf_on_device = 2
+    assert L.omc_set_source(eng._h, C.byref(s)) == omc.OMC_EINVAL
+    # a beamlet with bad device records names the beamlet
+    with pytest.raises(omc.OmcError) as e:
+        eng.run_beamlets([(good, 10, 0), (W.psf_source(bad), 10, 10)])
+    assert "beamlet 1" in str(e.value)
+    # the previous source is still in place
+    d, _ = eng.run(2000, seed=1)
+    c = eng.counters()
+    eng.close()
+    assert d.sum() > 0 and c["E_incident"] > 0
+    del keep
