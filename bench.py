@@ -47,6 +47,16 @@ WORKLOADS = {
     "slab_6mv_psf": "the slab_6mv beam read from a phase space: 2^20 synthetic records (6 MV "
                     "spectrum, 10x10 cm2 from SSD 100 cm, 1 degree spread, 2 % pointing away) "
                     "on the plane 1 cm above the 128^3 slab, 1e7 histories per step",
+    "layers8_6mv": "6 MV photons, 10x10 cm2 at SSD 100 cm, 80x64x64 phantom of 0.5 cm voxels "
+                   "in eight slabs along z, one per library material (water, lung, cortical "
+                   "bone, adipose, muscle, cartilage, spongiosa, air), 2e6 histories per step",
+    "layers16_6mv": "as layers8_6mv on 96x64x64 voxels with sixteen slabs: the 16-material "
+                    "library (the eight above, compact bone, skin, brain, blood, breast, "
+                    "liver, red marrow, soft tissue), 2e6 histories per step",
+    "ct_6mv": "6 MV photons, 10x10 cm2 at SSD 100 cm on a synthetic 256x256x160 CT volume of "
+              "0.2 cm voxels (body, fat, lungs, organs, bone column, noise) mapped on the "
+              "device to density and the 16-material library (13 present), 1e7 histories "
+              "per step",
     "water_e15": "15 MeV electrons, 1x1 cm2 parallel beam, 32^3 water of 0.5 cm voxels, "
                  "1e4 histories per step",
     "halfslab_e15": "15 MeV electrons, 10x10 cm2 at SSD 100 cm, 256^3 half-slab of 0.2 cm voxels, "
@@ -90,6 +100,9 @@ def denoiser_flops(n):
 SHAPES = {
     "slab_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
     "slab_6mv_psf": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
+    "layers8_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 4},
+    "layers16_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 4},
+    "ct_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
     "water_e15": {"graph_depth": 8, "chunk_histories": 0, "blocks_per_cu": 4},
     "halfslab_e15": {"graph_depth": 6, "chunk_histories": 0, "blocks_per_cu": 8},
 }
@@ -100,6 +113,10 @@ def cpu_baseline(ph, src, target_s, threads, params=None):
     workload, as it stands."""
     from oracle import oracle
     oracle.lib()
+    if "density" not in ph:
+        # a CT volume: the oracle's own mapping gives the phantom it transports
+        from oracle import ct
+        ph = ct.phantom(ph["hu"], ph["voxel"], ph["materials"], ph["ct_map"])
     # calibrate on two sizes so that the fixed set-up cost (tables, grids) is
     # separated from the per-history cost
     sizes, times = (20_000, 200_000), []
@@ -237,6 +254,9 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--straggler-lanes", type=int, default=-1)
+    ap.add_argument("--table-mode", type=int, default=0,
+                    help="per-material tables: 0 LDS while two work-groups fit a CU with "
+                         "them, else global memory; 1 LDS; 2 global memory")
     ap.add_argument("--electron-mode", type=int, default=0,
                     help="0: voxel-limited electron steps (the method); 1: fixed steps "
                          "across voxels (the gDPM scheme it is compared with)")
@@ -298,6 +318,8 @@ def main():
         shape["straggler_lanes"] = args.straggler_lanes
     if args.electron_mode:
         shape["electron_mode"] = args.electron_mode
+    if args.table_mode:
+        shape["table_mode"] = args.table_mode
     eng = omc.Engine(ph)
     eng.set_source(src)
     eng.set_params(parity_fp64=int(args.parity_fp64), **shape)
@@ -338,6 +360,7 @@ def main():
     value = n * args.steps / elapsed
     c = eng.counters()
     params = eng.params.as_dict()
+    tables = "global memory" if eng.timing()["tables_global"] else "LDS"
 
     out = {"metric": "histories/s", "value": value, "unit": "histories/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -348,6 +371,7 @@ def main():
                       "tally": "fp64",
                       "electron_steps": ("fixed, across voxels" if params["electron_mode"]
                                          else "voxel-limited"),
+                      "material_tables": tables,
                       "launch": {k: params[k] for k in ("block_size", "blocks_per_cu",
                                                         "chunk_histories", "graph_depth",
                                                         "queue_factor", "straggler_lanes")}}}

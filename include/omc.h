@@ -39,7 +39,7 @@ enum {
     OMC_EUNSUP = -7    /* unsupported configuration (e.g. too many materials) */
 };
 
-#define OMC_MAX_MATERIALS 8
+#define OMC_MAX_MATERIALS 32
 #define OMC_MAX_DIM 1024
 #define OMC_MAX_BATCHES 64
 #define OMC_NE 512      /* energy nodes, uniform in log2 E over [0.01, 20] MeV */
@@ -145,6 +145,12 @@ typedef struct {
                                 crosses, density scaling only), limited by dmax_s at unit
                                 density, f_E, E_abs and the hard-event mean free path, and
                                 each voxel on its path receives the CSDA loss inside it (0) */
+    int table_mode;          /* where the transport kernels read the per-material tables of
+                                the materials present in the phantom: 1 in LDS, staged per
+                                work-group (Sec. 2.2.2 keeps them in image memory; fails with
+                                OMC_EUNSUP when they exceed a work-group's LDS); 2 in global
+                                memory, through L2; 0 LDS while two work-groups still fit a
+                                CU with them, else global (0). Results do not depend on it */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */
@@ -168,14 +174,18 @@ typedef struct {
     uint32_t launches[4];    /* 0 source, 1 photon, 2 electron, 3 fold or compaction */
     double total_ms[4];
     double run_ms;           /* whole run, first launch to last */
+    int tables_global;       /* 1: the per-material tables were read from global memory
+                                (params.table_mode), 0: staged in LDS; set by every run */
 } omc_timing;
 
 void omc_default_params(omc_params* p);
 
 /* Create a context on the current HIP device. density: g/cm^3, finite and > 0;
- * material: ids < n_mats; mats: n_mats compositions (1 <= n_mats <= 8). Sizes:
- * 1 <= nx,ny,nz <= 1024, voxel sizes > 0. Builds the closed-form tables
- * (Sec. 2.1) and uploads phantom and tables. */
+ * material: ids < n_mats; mats: the material library, n_mats compositions
+ * (1 <= n_mats <= OMC_MAX_MATERIALS; Sec. 2.1 supports 16, built from
+ * user-defined compositions). Sizes: 1 <= nx,ny,nz <= 1024, voxel sizes > 0.
+ * Builds the closed-form tables (Sec. 2.1) and uploads the phantom; the device
+ * holds the tables of the materials present in the phantom only. */
 int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
                const float* density, const uint8_t* material, const omc_material* mats,
                int n_mats);
@@ -185,6 +195,35 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
  * tables of the materials are kept; the photon majorant, which depends on
  * the largest density of each material, is rebuilt. */
 int omc_set_phantom(omc_ctx* ctx, const float* density, const uint8_t* material);
+
+/* CT to phantom (Sec. 2.1: each voxel's density and material obtained from the
+ * patient's CT by a mapping method, Schneider et al. 2000). Density: piecewise
+ * linear in HU through the calibration nodes, the end node's density outside
+ * them; on the segment hu[k] <= h < hu[k+1] it is, in FP64 with one rounding
+ * per operation, rho[k] + (h - hu[k]) * ((rho[k+1] - rho[k]) / (hu[k+1] -
+ * hu[k])), then rounded once to FP32. Material: material[b] of the first bin b
+ * with h < hu_upper[b], the last bin when there is none. */
+#define OMC_MAX_CT_NODES 64
+typedef struct {
+    int n_nodes;             /* calibration nodes, 2 .. OMC_MAX_CT_NODES */
+    const double* hu;        /* n_nodes HU values, finite, strictly increasing */
+    const double* rho;       /* n_nodes densities, g/cm^3, in [1e-6, 100] */
+    int n_bins;              /* material bins, 1 .. OMC_MAX_MATERIALS */
+    const double* hu_upper;  /* n_bins upper bounds, increasing (the last is not read) */
+    const int* material;     /* n_bins library ids, < n_mats */
+} omc_ct_map;
+
+/* Replace the phantom's densities and materials by the mapping of a CT volume
+ * hu (int16 HU, nx * ny * nz values, x fastest), mapped on the device. hu is
+ * host memory (hu_on_device = 0, copied) or device memory on the context's
+ * device (1; read once during the call, which must lie inside one allocation
+ * holding every value, else OMC_EINVAL before any kernel reads it). Map errors
+ * give OMC_EINVAL with the context unchanged. Synchronous. */
+int omc_set_phantom_ct(omc_ctx* ctx, const int16_t* hu, int hu_on_device, const omc_ct_map* map);
+
+/* Copy the phantom as the device holds it into host arrays of nx * ny * nz
+ * densities (g/cm^3) and material ids (library ids), x fastest. Synchronous. */
+int omc_get_phantom(const omc_ctx* ctx, float* density, uint8_t* material);
 
 /* Set the source (copied). Spectrum weights must have a positive sum. */
 int omc_set_source(omc_ctx* ctx, const omc_source* src);

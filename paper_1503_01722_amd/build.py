@@ -6,6 +6,7 @@ Translation units:
   kernels_f64.hip  the parity instantiation, without FMA contraction
   runtime.cpp      host runtime and the C ABI of include/omc.h
   tables.cpp       closed-form physics tables (host, FP64)
+  phantom_kernels.hip  voxel records and the CT mapping, without FMA contraction
   dn_kernels.hip   denoiser kernels (BF16 matrix-core convolutions, loss, Adam)
   dn_runtime.cpp   denoiser network, training and the C ABI of include/omc_dn.h
 """
@@ -29,6 +30,7 @@ UNITS = {
     "kernels_f64.hip": ["-munsafe-fp-atomics", "-ffp-contract=off"],
     "runtime.cpp": ["-ffp-contract=off"],
     "tables.cpp": ["-ffp-contract=off"],
+    "phantom_kernels.hip": ["-ffp-contract=off"],
     "dn_kernels.hip": ["-munsafe-fp-atomics"],
     "dn_runtime.cpp": [],
 }

@@ -1,11 +1,13 @@
 // engine.hpp -- data shared by the host runtime and the gfx950 kernels.
 //
 // Layout in HBM (all allocations made once per context, sized for the run):
-//   phantom     rho f32[nvox], mat u8[nvox]                x fastest
-//   tables      photon  R4[n_mats][NE]  {mu_tot, mu_C, mu_PE, 0}   (cm^2/g)
-//               majorant R[NE]                                     (1/cm)
-//               electron R4[n_mats][NE] {R, sigma_hat, sigma_M, sigma_B}
-//               K1 R[n_mats][NE], ms log2 A R[NA], R(E_abs) R[n_mats]
+//   phantom     rho f32[nvox], mat u8[nvox] (library ids)    x fastest
+//               vox u32x2[nvox] {rho bits, table slot}       transport copy
+//   tables      for the materials present in the phantom (slots, library
+//               order): photon R4[n][NE] {mu_tot, mu_C, mu_PE, 0} (cm^2/g),
+//               majorant R[NE] (1/cm), electron R2[n][NE] {K1, sigma_hat},
+//               hard R2[n][NE] {sigma_M, sigma_B}, range R[n][NE] and its
+//               u16 cell index [n][kRangeCells], ms log2 A R[NA], R(E_abs) R[n]
 //   queues      four structure-of-arrays particle queues (photon cur/next,
 //               electron cur/next), each {x,y,z,u,v,w,E} R, voxel u32 packed
 //               (ix | iy<<10 | iz<<20), history u32, particle id 2 x u32,
@@ -24,6 +26,10 @@
 #include <cstdint>
 
 namespace omc {
+
+constexpr int kMaxMaterials = 32;  // materials of a context's library
+constexpr int kMaxCtNodes = 64;    // HU -> density calibration nodes
+constexpr int kMaxCtBins = 32;     // HU -> material bins
 
 enum Counter : int {
     C_PH_FLIGHTS = 0,
@@ -196,29 +202,33 @@ struct KernelArgs {
     int spill_lanes;      // a wave with at most this many live lanes left sets them aside (0: off)
 };
 
-// LDS bytes a transport work-group stages (tables of all materials).
+// LDS bytes a transport work-group stages: the tables of every material the
+// phantom holds, or (gtab: the per-material tables read from global memory,
+// through L2) only the photon majorant, the scattering table and R(E_abs).
 template <typename R>
-inline size_t photon_lds_bytes(int n_mats)
+inline size_t photon_lds_bytes(int n_mats, bool gtab = false)
 {
-    return 4 * sizeof(R) * size_t(n_mats) * kTabNE + sizeof(R) * kTabNE;
+    return (gtab ? 0 : 4 * sizeof(R) * size_t(n_mats) * kTabNE) + sizeof(R) * kTabNE;
 }
 template <typename R>
-inline size_t electron_lds_bytes(int n_mats)
+inline size_t electron_lds_bytes(int n_mats, bool gtab = false)
 {
-    return 2 * sizeof(R) * size_t(n_mats) * kTabNE + sizeof(R) * size_t(n_mats) * kTabNE +
-           sizeof(R) * kTabNA + sizeof(R) * ((size_t(n_mats) + 7) & ~size_t(7)) +
-           sizeof(uint16_t) * size_t(n_mats) * kRangeCells;
+    return (gtab ? 0
+                 : 2 * sizeof(R) * size_t(n_mats) * kTabNE + sizeof(R) * size_t(n_mats) * kTabNE +
+                       sizeof(uint16_t) * size_t(n_mats) * kRangeCells) +
+           sizeof(R) * kTabNA + sizeof(R) * ((size_t(n_mats) + 7) & ~size_t(7));
 }
 
 // Host-side launchers (one instantiation per precision).
 template <typename R>
 struct Launch {
-    static int prepare(size_t lds_ph, size_t lds_el);
+    static int prepare(size_t lds_ph, size_t lds_el, bool gtab);
     static int source(const KernelArgs<R>& a, int grid, int block, void* stream);
-    static int photon(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream);
+    static int photon(const KernelArgs<R>& a, int grid, int block, size_t lds, bool gtab,
+                      void* stream);
     // fixed: steps across voxels (electron_mode 1), a kernel of its own
     static int electron(const KernelArgs<R>& a, int grid, int block, size_t lds, bool fixed,
-                        void* stream);
+                        bool gtab, void* stream);
 };
 
 int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,
@@ -256,6 +266,15 @@ int launch_compact_write(const double* grid, const float* rho, size_t nvox, int 
 // out[0] += 1 and out[1] = min(out[1], k) for every bad record k (energy not in
 // (0, ehi), a non-finite position or direction component, a zero direction).
 int launch_check_records(const float* rec, uint32_t n, double ehi, uint32_t* out, void* stream);
+// Phantom (phantom_kernels.hip): vox[v] = {rho[v] bits, slot[mat[v]]}; and the
+// CT mapping of nvox HU values into rho and mat (library ids) with the largest
+// density bits of each material atomically raised in rmax_bits[kMaxMaterials].
+// map holds n_nodes HU nodes, n_nodes densities and n_bins bin upper bounds.
+int launch_build_vox(const float* rho, const uint8_t* mat, size_t nvox, const uint32_t* slot,
+                     uint32_t* vox, void* stream);
+int launch_ct_map(const int16_t* hu, size_t nvox, const double* map, const uint32_t* bin_mat,
+                  int n_nodes, int n_bins, float* rho, uint8_t* mat, uint32_t* rmax_bits,
+                  void* stream);
 int launch_philox_debug(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
                         uint32_t* out, void* stream);
 

@@ -23,38 +23,52 @@ int Launch<R>::source(const KernelArgs<R>& a, int grid, int block, void* stream)
 // Allow more than 64 KB of dynamic LDS where the tables need it (done before
 // any launch, outside stream capture).
 template <typename R>
-int Launch<R>::prepare(size_t lds_ph, size_t lds_el)
+int Launch<R>::prepare(size_t lds_ph, size_t lds_el, bool gtab)
 {
-    if (lds_ph > 65536 &&
-        hipFuncSetAttribute((const void*)photon_kernel<R>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_ph)) != hipSuccess)
-        return -1;
-    if (lds_el > 65536 &&
-        (hipFuncSetAttribute((const void*)electron_kernel<R, false>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_el)) != hipSuccess ||
-         hipFuncSetAttribute((const void*)electron_kernel<R, true>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_el)) != hipSuccess))
-        return -1;
-    return 0;
+    auto raise = [](const void* f, size_t lds) {
+        return lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  int(lds)) != hipSuccess;
+    };
+    if (gtab)
+        return raise((const void*)photon_kernel<R, true>, lds_ph) ||
+                       raise((const void*)electron_kernel<R, false, true>, lds_el) ||
+                       raise((const void*)electron_kernel<R, true, true>, lds_el)
+                   ? -1
+                   : 0;
+    return raise((const void*)photon_kernel<R, false>, lds_ph) ||
+                   raise((const void*)electron_kernel<R, false, false>, lds_el) ||
+                   raise((const void*)electron_kernel<R, true, false>, lds_el)
+               ? -1
+               : 0;
 }
 
 template <typename R>
-int Launch<R>::photon(const KernelArgs<R>& a, int grid, int block, size_t lds, void* stream)
+int Launch<R>::photon(const KernelArgs<R>& a, int grid, int block, size_t lds, bool gtab,
+                      void* stream)
 {
-    hipLaunchKernelGGL(photon_kernel<R>, dim3(grid), dim3(block), lds, (hipStream_t)stream, a);
+    if (gtab)
+        hipLaunchKernelGGL((photon_kernel<R, true>), dim3(grid), dim3(block), lds,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL((photon_kernel<R, false>), dim3(grid), dim3(block), lds,
+                           (hipStream_t)stream, a);
     return detail::launch_status();
 }
 
 template <typename R>
 int Launch<R>::electron(const KernelArgs<R>& a, int grid, int block, size_t lds, bool fixed,
-                        void* stream)
+                        bool gtab, void* stream)
 {
-    if (fixed)
-        hipLaunchKernelGGL((electron_kernel<R, true>), dim3(grid), dim3(block), lds,
-                           (hipStream_t)stream, a);
+    const hipStream_t s = (hipStream_t)stream;
+    if (fixed && gtab)
+        hipLaunchKernelGGL((electron_kernel<R, true, true>), dim3(grid), dim3(block), lds, s, a);
+    else if (fixed)
+        hipLaunchKernelGGL((electron_kernel<R, true, false>), dim3(grid), dim3(block), lds, s, a);
+    else if (gtab)
+        hipLaunchKernelGGL((electron_kernel<R, false, true>), dim3(grid), dim3(block), lds, s, a);
     else
-        hipLaunchKernelGGL((electron_kernel<R, false>), dim3(grid), dim3(block), lds,
-                           (hipStream_t)stream, a);
+        hipLaunchKernelGGL((electron_kernel<R, false, false>), dim3(grid), dim3(block), lds, s,
+                           a);
     return detail::launch_status();
 }
 

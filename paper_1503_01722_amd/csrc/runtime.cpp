@@ -69,10 +69,13 @@ struct omc_ctx {
     int nx = 0, ny = 0, nz = 0;
     double dx = 0, dy = 0, dz = 0;
     size_t nvox = 0;
-    std::vector<float> rho;
-    std::vector<uint8_t> mat;
     std::vector<omc::MaterialSpec> mats;
     std::vector<double> rho_max;  // per material
+    // table slots: the device tables hold the materials present in the phantom
+    // only, in library order; the voxel records carry the slot
+    std::vector<int> present;     // slot -> library material
+    std::vector<uint32_t> slot_of;  // library material -> slot (absent: 0)
+    bool last_gtab = false;       // the last run read its tables from global memory
 
     bool has_source = false;
     std::vector<float> psf;  // phase-space records of the source (geometry 2)
@@ -83,7 +86,8 @@ struct omc_ctx {
     int cu_count = 0;
     float* d_rho = nullptr;
     uint8_t* d_mat = nullptr;
-    uint32_t* d_vox = nullptr;  // [nvox][2]: density bits, material id
+    uint32_t* d_vox = nullptr;  // [nvox][2]: density bits, table slot
+    uint32_t* d_slot = nullptr;  // [kMaxMaterials] slot of each library material
     double* d_grid = nullptr;
     size_t grid_cells = 0;      // tally cells d_grid holds (nvox doubles each)
     char* d_src = nullptr;      // beams, history prefix, spectra of the current job
@@ -288,12 +292,12 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
 {
     host_tables(c);
     if (t.valid) return OMC_OK;
-    const int nm = int(c->mats.size());
+    const int nm = int(c->present.size());
     const int NE = omc::kNE;
     std::vector<R> ph(size_t(nm) * NE * 4), el(size_t(nm) * NE * 2), hard(size_t(nm) * NE * 2),
         rtab(size_t(nm) * NE), muhat(NE), msA(omc::kNA), Rabs(nm);
     for (int m = 0; m < nm; ++m) {
-        const auto& T = c->tabs[m];
+        const auto& T = c->tabs[c->present[m]];
         for (int i = 0; i < NE; ++i) {
             const size_t o = (size_t(m) * NE + i) * 4;
             ph[o + 0] = R(T.muTot[i]);
@@ -307,13 +311,13 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
             hard[o2 + 1] = R(T.sigB[i]);
             rtab[size_t(m) * NE + i] = R(T.R[i]);
         }
-        Rabs[m] = R(c->Rabs[m]);
+        Rabs[m] = R(c->Rabs[c->present[m]]);
     }
     // photon majorant over the materials present: node-wise max of
     // rho_max(m) * mu_tot(m), whose interpolant bounds every material's
     for (int i = 0; i < NE; ++i) {
         double mx = 0.0;
-        for (int m = 0; m < nm; ++m) mx = std::max(mx, c->rho_max[m] * c->tabs[m].muTot[i]);
+        for (int m : c->present) mx = std::max(mx, c->rho_max[m] * c->tabs[m].muTot[i]);
         muhat[i] = R(mx);
     }
     for (int j = 0; j < omc::kNA; ++j) msA[j] = R(c->ms[j]);
@@ -598,20 +602,26 @@ int check_source(const omc_source* s, std::vector<double>& edges, std::vector<do
 // Device records (psf_on_device): the pointer must lie in a HIP allocation on the
 // context's device that holds all n records; then every record is checked on
 // the device with the host's conditions, before any kernel reads them.
-int check_device_records(omc_ctx* c, const float* p, int n, std::string& why)
+// True when [p, p + bytes) lies inside one HIP allocation of the context's
+// device (a caller's device buffer, checked before any kernel reads it).
+bool device_range_ok(const omc_ctx* c, const void* p, size_t bytes, size_t align)
 {
     hipPointerAttribute_t at{};
     hipDeviceptr_t base = nullptr;
     size_t size = 0;
-    const size_t bytes = size_t(n) * 8 * sizeof(float);
     const bool dev = hipPointerGetAttributes(&at, p) == hipSuccess &&
                      at.type == hipMemoryTypeDevice && at.device == c->device;
     const bool range =
-        dev && hipMemGetAddressRange(&base, &size, const_cast<float*>(p)) == hipSuccess &&
+        dev && hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess &&
         reinterpret_cast<uintptr_t>(p) >= reinterpret_cast<uintptr_t>(base) &&
         reinterpret_cast<uintptr_t>(p) + bytes <= reinterpret_cast<uintptr_t>(base) + size;
     (void)hipGetLastError();
-    if (!dev || !range || reinterpret_cast<uintptr_t>(p) % alignof(float)) {
+    return dev && range && reinterpret_cast<uintptr_t>(p) % align == 0;
+}
+
+int check_device_records(omc_ctx* c, const float* p, int n, std::string& why)
+{
+    if (!device_range_ok(c, p, size_t(n) * 8 * sizeof(float), alignof(float))) {
         why = "psf_on_device: the records must be an allocation of this context's device "
               "holding n_psf x 8 floats";
         return OMC_EINVAL;
@@ -840,7 +850,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     a.tab.rcells = T.rcells;
     a.tab.msA = T.msA;
     a.tab.Rabs = T.Rabs;
-    a.tab.n_mats = int(c->mats.size());
+    a.tab.n_mats = int(c->present.size());
     a.tab.L0 = R(g.L0);
     a.tab.DL = R(g.DL);
     a.tab.INV = R(g.INV);
@@ -866,16 +876,26 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
 
     const int block = P.block_size;
     const int tgrid = c->cu_count * P.blocks_per_cu;
-    const int nm = int(c->mats.size());
-    const size_t lds_ph = omc::photon_lds_bytes<R>(nm);
-    const size_t lds_el = omc::electron_lds_bytes<R>(nm);
-    int lds_max = 0;
+    const int nm = int(c->present.size());
+    int lds_max = 0, lds_cu = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    HIP_TRY(c, hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                     c->device));
+    // per-material tables in LDS while two work-groups of each kernel still fit
+    // a CU with them; else read from global memory (through L2). On MI355X, 8
+    // materials (66 KB in FP32, two work-groups) run faster from LDS at 4 to 8
+    // requested work-groups per CU, 16 (130 KB, one work-group) from global
+    const size_t lds_tabs = std::max(omc::photon_lds_bytes<R>(nm), omc::electron_lds_bytes<R>(nm));
+    const bool gtab = P.table_mode == 2 || (P.table_mode == 0 && 2 * lds_tabs > size_t(lds_cu));
+    const size_t lds_ph = omc::photon_lds_bytes<R>(nm, gtab);
+    const size_t lds_el = omc::electron_lds_bytes<R>(nm, gtab);
     if (lds_ph > size_t(lds_max) || lds_el > size_t(lds_max))
-        return fail(c, OMC_EUNSUP, "material tables exceed the LDS of a work-group; use fewer "
-                                   "materials (or the FP32 build)");
-    if (omc::Launch<R>::prepare(lds_ph, lds_el))
+        return fail(c, OMC_EUNSUP, "material tables exceed the LDS of a work-group; use "
+                                   "table_mode 0 or 2 (tables in global memory)");
+    if (omc::Launch<R>::prepare(lds_ph, lds_el, gtab))
         return fail(c, OMC_EDEVICE, "cannot raise the LDS limit of the transport kernels");
+    c->last_gtab = gtab;
+    c->timing.tables_global = gtab ? 1 : 0;
 
     auto zero_all = [&](hipStream_t st) {
         return omc::launch_zero(c->d_grid, need, st) ||
@@ -901,14 +921,15 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
             a.qe_out = Q.q[ec];
             a.qp_out = Q.q[pc ^ 1];
             t.begin(1);
-            e = omc::Launch<R>::photon(a, tgrid, block, lds_ph, st);
+            e = omc::Launch<R>::photon(a, tgrid, block, lds_ph, gtab, st);
             t.end();
         }
         a.qin = Q.q[ec];
         a.qe_out = Q.q[ec ^ 1];
         a.qp_out = Q.q[pc ^ 1];
         t.begin(2);
-        e = e || omc::Launch<R>::electron(a, tgrid, block, lds_el, P.electron_mode == 1, st);
+        e = e || omc::Launch<R>::electron(a, tgrid, block, lds_el, P.electron_mode == 1, gtab,
+                                          st);
         t.end();
         return e || omc::launch_queue_reset(c->d_ctrl, (1 << pc) | (1 << ec), st);
     };
@@ -976,7 +997,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         const uint64_t shape[16] = {sizeof(R), N,      S,      uint64_t(K), uint64_t(block),
                                     uint64_t(tgrid),   lds_ph, lds_el,      uint64_t(P.timing),
                                     uint64_t(job.particle), need, uint64_t(P.electron_mode),
-                                    0, 0, 0, 0};
+                                    uint64_t(gtab), 0, 0, 0};
         std::memcpy(key.data(), &a, sizeof a);
         std::memcpy(key.data() + sizeof a, shape, sizeof shape);
         if (!c->graph || key != c->graph_key) {
@@ -1338,9 +1359,12 @@ void omc_default_params(omc_params* p)
     p->sparse_threshold = 0.0;
     p->straggler_lanes = 16;
     p->electron_mode = 0;
+    p->table_mode = 0;
 }
 
-int upload_phantom(omc_ctx* c);
+int check_phantom(const float* density, const uint8_t* material, size_t nvox, int n_mats,
+                  std::vector<double>& rmax);
+int upload_phantom(omc_ctx* c, const float* density, const uint8_t* material);
 
 int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
                const float* density, const uint8_t* material, const omc_material* mats,
@@ -1372,17 +1396,9 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
             return fail(nullptr, OMC_EINVAL, why);
         }
     }
-    c->rho.assign(density, density + c->nvox);
-    c->mat.assign(material, material + c->nvox);
-    c->rho_max.assign(n_mats, 0.0);
-    for (size_t v = 0; v < c->nvox; ++v) {
-        const float r = c->rho[v];
-        if (!(std::isfinite(r) && r > 0.0f) || c->mat[v] >= n_mats) {
-            delete c;
-            return fail(nullptr, OMC_EINVAL,
-                        "density must be finite and > 0 and material ids < n_mats");
-        }
-        c->rho_max[c->mat[v]] = std::max(c->rho_max[c->mat[v]], double(r));
+    if (check_phantom(density, material, c->nvox, n_mats, c->rho_max)) {
+        delete c;
+        return fail(nullptr, OMC_EINVAL, "density must be finite and > 0 and material ids < n_mats");
     }
     omc_default_params(&c->prm);
 
@@ -1407,8 +1423,9 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
               hipHostMalloc(&c->h_ctrl, 64 * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->d_run, sizeof(omc::RunDesc)) == hipSuccess &&
               hipHostMalloc(&c->h_run, sizeof(omc::RunDesc)) == hipSuccess;
-    ok = ok && hipMalloc(&c->d_vox, c->nvox * 2 * sizeof(uint32_t)) == hipSuccess;
-    ok = ok && upload_phantom(c) == OMC_OK;
+    ok = ok && hipMalloc(&c->d_vox, c->nvox * 2 * sizeof(uint32_t)) == hipSuccess &&
+         hipMalloc(&c->d_slot, omc::kMaxMaterials * sizeof(uint32_t)) == hipSuccess;
+    ok = ok && upload_phantom(c, density, material) == OMC_OK;
     if (!ok) {
         omc_destroy(c);
         return fail(nullptr, OMC_ENOMEM, "device allocation or upload failed");
@@ -1417,41 +1434,142 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
     return OMC_OK;
 }
 
-// Densities and materials to the device: the two plain arrays (dose
-// conversion, compaction) and the interleaved voxel records of the transport.
-int upload_phantom(omc_ctx* c)
+// Host densities and materials: finite and > 0, ids below n_mats; the
+// largest density of each material (0 where it is absent).
+int check_phantom(const float* density, const uint8_t* material, size_t nvox, int n_mats,
+                  std::vector<double>& rmax)
 {
-    std::vector<uint32_t> vox(c->nvox * 2);
-    for (size_t v = 0; v < c->nvox; ++v) {
-        std::memcpy(&vox[2 * v], &c->rho[v], sizeof(float));
-        vox[2 * v + 1] = c->mat[v];
+    rmax.assign(n_mats, 0.0);
+    for (size_t v = 0; v < nvox; ++v) {
+        const float r = density[v];
+        if (!(std::isfinite(r) && r > 0.0f) || material[v] >= n_mats) return OMC_EINVAL;
+        rmax[material[v]] = std::max(rmax[material[v]], double(r));
     }
-    HIP_TRY(c, hipMemcpy(c->d_rho, c->rho.data(), c->nvox * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_mat, c->mat.data(), c->nvox, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->d_vox, vox.data(), vox.size() * sizeof(uint32_t),
-                         hipMemcpyHostToDevice));
     return OMC_OK;
+}
+
+// The transport's voxel records from d_rho and d_mat: the tables hold the
+// materials present (densities are > 0, so where the maximum is), in library
+// order, and a voxel carries its material's slot. Synchronous, so that any
+// stream may run next.
+int build_vox(omc_ctx* c)
+{
+    c->present.clear();
+    c->slot_of.assign(c->mats.size(), 0u);
+    for (size_t m = 0; m < c->mats.size(); ++m)
+        if (c->rho_max[m] > 0.0) {
+            c->slot_of[m] = uint32_t(c->present.size());
+            c->present.push_back(int(m));
+        }
+    uint32_t slot[omc::kMaxMaterials] = {};
+    for (size_t m = 0; m < c->slot_of.size(); ++m) slot[m] = c->slot_of[m];
+    HIP_TRY(c, hipMemcpy(c->d_slot, slot, sizeof slot, hipMemcpyHostToDevice));
+    if (omc::launch_build_vox(c->d_rho, c->d_mat, c->nvox, c->d_slot, c->d_vox, nullptr))
+        return fail(c, OMC_EDEVICE, "voxel record launch failed");
+    HIP_TRY(c, hipStreamSynchronize(nullptr));
+    // the majorant and the table slots depend on the phantom: new tables next run
+    c->t32.valid = false;
+    c->t64.valid = false;
+    return OMC_OK;
+}
+
+// Host densities and materials to the device, then the voxel records.
+int upload_phantom(omc_ctx* c, const float* density, const uint8_t* material)
+{
+    HIP_TRY(c, hipMemcpy(c->d_rho, density, c->nvox * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_mat, material, c->nvox, hipMemcpyHostToDevice));
+    return build_vox(c);
 }
 
 int omc_set_phantom(omc_ctx* c, const float* density, const uint8_t* material)
 {
     if (check_ctx(c) || !density || !material) return fail(c, OMC_EINVAL, "NULL argument");
-    const int nm = int(c->mats.size());
-    std::vector<double> rmax(nm, 0.0);
-    for (size_t v = 0; v < c->nvox; ++v) {
-        const float r = density[v];
-        if (!(std::isfinite(r) && r > 0.0f) || material[v] >= nm)
-            return fail(c, OMC_EINVAL, "density must be finite and > 0 and material ids < n_mats");
-        rmax[material[v]] = std::max(rmax[material[v]], double(r));
-    }
+    std::vector<double> rmax;
+    if (check_phantom(density, material, c->nvox, int(c->mats.size()), rmax))
+        return fail(c, OMC_EINVAL, "density must be finite and > 0 and material ids < n_mats");
     HIP_TRY(c, hipSetDevice(c->device));
-    c->rho.assign(density, density + c->nvox);
-    c->mat.assign(material, material + c->nvox);
     c->rho_max = rmax;
-    if (int rc = upload_phantom(c)) return rc;
-    // the majorant depends on rho_max: rebuild the device tables on the next run
-    c->t32.valid = false;
-    c->t64.valid = false;
+    return upload_phantom(c, density, material);
+}
+
+int omc_set_phantom_ct(omc_ctx* c, const int16_t* hu, int hu_on_device, const omc_ct_map* map)
+{
+    if (check_ctx(c) || !hu || !map) return fail(c, OMC_EINVAL, "NULL argument");
+    const int nn = map->n_nodes, nb = map->n_bins;
+    if (nn < 2 || nn > omc::kMaxCtNodes || !map->hu || !map->rho)
+        return fail(c, OMC_EINVAL, "a CT map needs 2 <= n_nodes <= 64 calibration nodes");
+    for (int k = 0; k < nn; ++k) {
+        if (!std::isfinite(map->hu[k]) || (k > 0 && !(map->hu[k] > map->hu[k - 1])))
+            return fail(c, OMC_EINVAL, "CT calibration HU values must be finite and increasing");
+        if (!(map->rho[k] >= 1e-6 && map->rho[k] <= 100.0))
+            return fail(c, OMC_EINVAL, "CT calibration densities must be in [1e-6, 100] g/cm3");
+    }
+    if (nb < 1 || nb > omc::kMaxCtBins || !map->material || (nb > 1 && !map->hu_upper))
+        return fail(c, OMC_EINVAL, "a CT map needs 1 <= n_bins <= 32 material bins");
+    for (int b = 0; b < nb; ++b) {
+        if (map->material[b] < 0 || map->material[b] >= int(c->mats.size()))
+            return fail(c, OMC_EINVAL, "CT bin material ids must be < n_mats");
+        if (b + 1 < nb && (std::isnan(map->hu_upper[b]) ||
+                           (b > 0 && !(map->hu_upper[b] > map->hu_upper[b - 1]))))
+            return fail(c, OMC_EINVAL, "CT bin upper bounds must be increasing");
+    }
+    if (hu_on_device != 0 && hu_on_device != 1)
+        return fail(c, OMC_EINVAL, "hu_on_device must be 0 or 1");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (hu_on_device && !device_range_ok(c, hu, c->nvox * sizeof(int16_t), alignof(int16_t)))
+        return fail(c, OMC_EINVAL, "hu_on_device: the HU values must be an allocation of this "
+                                   "context's device holding nx * ny * nz int16 values");
+    // map [hu][rho][upper], bin materials, per-material maxima, and host HU
+    std::vector<double> m(size_t(2 * nn + nb), 0.0);
+    for (int k = 0; k < nn; ++k) {
+        m[k] = map->hu[k];
+        m[nn + k] = map->rho[k];
+    }
+    for (int b = 0; b + 1 < nb; ++b) m[2 * nn + b] = map->hu_upper[b];
+    std::vector<uint32_t> bm(nb);
+    for (int b = 0; b < nb; ++b) bm[b] = uint32_t(map->material[b]);
+    const size_t o_mat = align256(m.size() * sizeof(double));
+    const size_t o_max = o_mat + align256(bm.size() * sizeof(uint32_t));
+    const size_t o_hu = o_max + align256(omc::kMaxMaterials * sizeof(uint32_t));
+    const size_t total = o_hu + (hu_on_device ? 0 : c->nvox * sizeof(int16_t));
+    char* buf = nullptr;
+    if (hipMalloc(&buf, total) != hipSuccess) return fail(c, OMC_ENOMEM, "hipMalloc failed for the CT map");
+    struct Guard {
+        char* p;
+        ~Guard() { dfree(p); }
+    } guard{buf};
+    const uint32_t zero[omc::kMaxMaterials] = {};
+    HIP_TRY(c, hipMemcpy(buf, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(buf + o_mat, bm.data(), bm.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(buf + o_max, zero, sizeof zero, hipMemcpyHostToDevice));
+    const int16_t* d_hu = hu;
+    if (!hu_on_device) {
+        HIP_TRY(c, hipMemcpy(buf + o_hu, hu, c->nvox * sizeof(int16_t), hipMemcpyHostToDevice));
+        d_hu = reinterpret_cast<const int16_t*>(buf + o_hu);
+    }
+    if (omc::launch_ct_map(d_hu, c->nvox, reinterpret_cast<const double*>(buf),
+                           reinterpret_cast<const uint32_t*>(buf + o_mat), nn, nb, c->d_rho,
+                           c->d_mat, reinterpret_cast<uint32_t*>(buf + o_max), nullptr))
+        return fail(c, OMC_EDEVICE, "CT mapping launch failed");
+    uint32_t mx[omc::kMaxMaterials];
+    HIP_TRY(c, hipMemcpy(mx, buf + o_max, sizeof mx, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < c->mats.size(); ++k) {
+        float r;
+        std::memcpy(&r, &mx[k], sizeof r);
+        c->rho_max[k] = double(r);
+    }
+    return build_vox(c);
+}
+
+int omc_get_phantom(const omc_ctx* c, float* density, uint8_t* material)
+{
+    if (!c || !density || !material) return fail(nullptr, OMC_EINVAL, "NULL argument");
+    if (hipSetDevice(c->device) != hipSuccess ||
+        hipMemcpy(density, c->d_rho, c->nvox * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(material, c->d_mat, c->nvox, hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(nullptr, OMC_EDEVICE, "cannot copy the phantom from the device");
+    }
     return OMC_OK;
 }
 
@@ -1503,6 +1621,8 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
         return fail(c, OMC_EINVAL, "straggler_lanes must be in 0..63");
     if (p->electron_mode != 0 && p->electron_mode != 1)
         return fail(c, OMC_EINVAL, "electron_mode must be 0 or 1");
+    if (p->table_mode < 0 || p->table_mode > 2)
+        return fail(c, OMC_EINVAL, "table_mode must be 0, 1 or 2");
     c->prm = *p;
     return OMC_OK;
 }
@@ -1857,6 +1977,7 @@ void omc_destroy(omc_ctx* c)
     dfree(c->d_rho);
     dfree(c->d_mat);
     dfree(c->d_vox);
+    dfree(c->d_slot);
     dfree(c->d_src);
     dfree(c->d_psf);
     dfree(c->d_chk);

@@ -19,7 +19,9 @@ NE = 512
 NA = 512
 TABLE_ROWS = ["muC", "muPE", "muPair", "muTot", "Scol", "Srad", "R", "sigM", "sigB", "sigHat",
               "K1"]
-EXPORTS = ["omc_default_params", "omc_create", "omc_set_phantom", "omc_set_source",
+EXPORTS = ["omc_default_params", "omc_create", "omc_set_phantom", "omc_set_phantom_ct",
+           "omc_get_phantom",
+           "omc_set_source",
            "omc_set_params",
            "omc_get_params", "omc_run", "omc_run_device", "omc_run_beamlets", "omc_free_sparse",
            "omc_autotune", "omc_get_counters", "omc_get_timing", "omc_debug_philox",
@@ -55,6 +57,12 @@ class Source(C.Structure):
                 ("n_psf", C.c_int), ("psf", C.POINTER(C.c_float)), ("psf_on_device", C.c_int)]
 
 
+class CtMap(C.Structure):
+    _fields_ = [("n_nodes", C.c_int), ("hu", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double)),
+                ("n_bins", C.c_int), ("hu_upper", C.POINTER(C.c_double)),
+                ("material", C.POINTER(C.c_int))]
+
+
 class Params(C.Structure):
     _fields_ = [("Eabs_e", C.c_double), ("Eabs_g", C.c_double), ("Wcc", C.c_double),
                 ("kc", C.c_double), ("dmax_s", C.c_double), ("f_E", C.c_double),
@@ -63,7 +71,7 @@ class Params(C.Structure):
                 ("chunk_histories", C.c_int), ("queue_factor", C.c_int), ("timing", C.c_int),
                 ("graph_depth", C.c_int), ("beamlet_group", C.c_int),
                 ("sparse_threshold", C.c_double), ("straggler_lanes", C.c_int),
-                ("electron_mode", C.c_int)]
+                ("electron_mode", C.c_int), ("table_mode", C.c_int)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -99,12 +107,14 @@ class Counters(C.Structure):
 
 
 class Timing(C.Structure):
-    _fields_ = [("launches", C.c_uint32 * 4), ("total_ms", C.c_double * 4), ("run_ms", C.c_double)]
+    _fields_ = [("launches", C.c_uint32 * 4), ("total_ms", C.c_double * 4), ("run_ms", C.c_double),
+                ("tables_global", C.c_int)]
 
     def as_dict(self):
         names = ["source", "photon", "electron", "fold"]
         return {"launches": dict(zip(names, list(self.launches))),
-                "total_ms": dict(zip(names, list(self.total_ms))), "run_ms": self.run_ms}
+                "total_ms": dict(zip(names, list(self.total_ms))), "run_ms": self.run_ms,
+                "tables_global": self.tables_global}
 
 
 _lib = None
@@ -133,6 +143,8 @@ def lib():
                                  C.c_double, C.POINTER(C.c_float), C.POINTER(C.c_uint8),
                                  C.POINTER(Material), C.c_int]
         L.omc_set_phantom.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint8)]
+        L.omc_set_phantom_ct.argtypes = [vp, vp, C.c_int, C.POINTER(CtMap)]
+        L.omc_get_phantom.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint8)]
         L.omc_set_source.argtypes = [vp, C.POINTER(Source)]
         L.omc_set_params.argtypes = [vp, C.POINTER(Params)]
         L.omc_get_params.argtypes = [vp, C.POINTER(Params)]
@@ -207,11 +219,19 @@ class Engine:
     """One phantom on the current HIP device (see omc_create)."""
 
     def __init__(self, phantom):
+        """phantom: {"shape" (z, y, x), "voxel", "materials", and either "density"
+        and "material" arrays or a CT volume "hu" with its "ct_map" (mapped on
+        the device by omc_set_phantom_ct)."""
         self.shape = tuple(phantom["shape"])
         nz, ny, nx = self.shape
         dz, dy, dx = phantom["voxel"]
-        dens = np.ascontiguousarray(phantom["density"], dtype=np.float32).ravel()
-        mat = np.ascontiguousarray(phantom["material"], dtype=np.uint8).ravel()
+        ct = "density" not in phantom and "hu" in phantom
+        if ct:
+            dens = np.ones(nz * ny * nx, np.float32)
+            mat = np.zeros(nz * ny * nx, np.uint8)
+        else:
+            dens = np.ascontiguousarray(phantom["density"], dtype=np.float32).ravel()
+            mat = np.ascontiguousarray(phantom["material"], dtype=np.uint8).ravel()
         holders = [_MaterialHolder(m) for m in phantom["materials"]]
         arr = (Material * len(holders))(*[h.struct for h in holders])
         h = C.c_void_p()
@@ -221,6 +241,8 @@ class Engine:
         _check(rc, None)
         self._h = h
         self.params = default_params()
+        if ct:
+            self.set_phantom_ct(phantom["hu"], phantom["ct_map"])
 
     def close(self):
         if getattr(self, "_h", None):
@@ -240,6 +262,43 @@ class Engine:
         mat = np.ascontiguousarray(phantom["material"], dtype=np.uint8).ravel()
         _check(lib().omc_set_phantom(self._h, dens.ctypes.data_as(C.POINTER(C.c_float)),
                                      mat.ctypes.data_as(C.POINTER(C.c_uint8))), self._h)
+
+    def set_phantom_ct(self, hu, ct_map):
+        """Densities and materials from a CT volume (omc_set_phantom_ct): hu is an
+        int16 array of the phantom's shape (z, y, x), on the host or a device
+        tensor; ct_map a dict with "hu", "rho" (calibration nodes), "upper" (bin
+        upper bounds) and "material" (library id per bin)."""
+        nodes = np.ascontiguousarray(ct_map["hu"], dtype=np.float64)
+        rho = np.ascontiguousarray(ct_map["rho"], dtype=np.float64)
+        upper = np.ascontiguousarray(ct_map["upper"], dtype=np.float64)
+        mats = np.ascontiguousarray(ct_map["material"], dtype=np.int32)
+        if len(nodes) != len(rho) or len(upper) != len(mats):
+            raise ValueError("ct_map: hu/rho and upper/material must pair up")
+        m = CtMap(len(nodes), _dptr(nodes), _dptr(rho), len(mats), _dptr(upper),
+                  mats.ctypes.data_as(C.POINTER(C.c_int)))
+        if getattr(hu, "is_cuda", False):
+            import torch
+            if hu.dtype != torch.int16 or not hu.is_contiguous() or \
+                    tuple(hu.shape) != self.shape:
+                raise ValueError("device HU must be a contiguous int16 tensor of the phantom's "
+                                 "shape")
+            ptr, on_dev = C.c_void_p(hu.data_ptr()), 1
+        else:
+            hu = np.ascontiguousarray(hu, dtype=np.int16)
+            if hu.shape != self.shape:
+                raise ValueError("HU volume must have the phantom's shape")
+            ptr, on_dev = hu.ctypes.data_as(C.c_void_p), 0
+        _check(lib().omc_set_phantom_ct(self._h, ptr, on_dev, C.byref(m)), self._h)
+
+    def get_phantom(self):
+        """The phantom's densities and material ids as the device holds them
+        (omc_get_phantom), shaped (z, y, x)."""
+        n = int(np.prod(self.shape))
+        dens = np.zeros(n, np.float32)
+        mat = np.zeros(n, np.uint8)
+        _check(lib().omc_get_phantom(self._h, dens.ctypes.data_as(C.POINTER(C.c_float)),
+                                     mat.ctypes.data_as(C.POINTER(C.c_uint8))), self._h)
+        return dens.reshape(self.shape), mat.reshape(self.shape)
 
     def set_source(self, src):
         s, keep = _source_struct(src)

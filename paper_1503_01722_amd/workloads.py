@@ -24,7 +24,7 @@ import numpy as np
 # Element data: (Z, atomic weight g/mol).
 _ELEM = {"H": (1, 1.008), "C": (6, 12.011), "N": (7, 14.007), "O": (8, 15.999),
          "Na": (11, 22.990), "Mg": (12, 24.305), "P": (15, 30.974), "S": (16, 32.06),
-         "Cl": (17, 35.45), "K": (19, 39.098), "Ca": (20, 40.078)}
+         "Cl": (17, 35.45), "K": (19, 39.098), "Ca": (20, 40.078), "Fe": (26, 55.845)}
 
 
 def _material(name, comp, I_eV, rho_nom):
@@ -62,6 +62,33 @@ SPONGIOSA = _material("spongiosa", [("H", 0.085), ("C", 0.404), ("N", 0.028), ("
                                     ("Cl", 0.002), ("K", 0.001), ("Ca", 0.074)], 85.0, 1.18)
 AIR = _material("air", [("C", 0.000124), ("N", 0.755268), ("O", 0.231781)], 85.7, 0.0012)
 MATERIALS_8 = MATERIALS + [ADIPOSE, MUSCLE, CARTILAGE, SPONGIOSA, AIR]
+
+# Eight more (ICRU-46-like values, approximate; the paper's 16-material database
+# is not given): the 16 materials of a radiotherapy library, ids 0..15.
+COMPACT_BONE = _material("compact bone", [("H", 0.064), ("C", 0.278), ("N", 0.027),
+                                          ("O", 0.410), ("Mg", 0.002), ("P", 0.070),
+                                          ("S", 0.002), ("Ca", 0.147)], 91.9, 1.85)
+SKIN = _material("skin", [("H", 0.100), ("C", 0.204), ("N", 0.042), ("O", 0.645), ("Na", 0.002),
+                          ("P", 0.001), ("S", 0.002), ("Cl", 0.003), ("K", 0.001)], 72.7, 1.09)
+BRAIN = _material("brain", [("H", 0.107), ("C", 0.145), ("N", 0.022), ("O", 0.712),
+                            ("Na", 0.002), ("P", 0.004), ("S", 0.002), ("Cl", 0.003),
+                            ("K", 0.003)], 73.3, 1.04)
+BLOOD = _material("blood", [("H", 0.102), ("C", 0.110), ("N", 0.033), ("O", 0.745),
+                            ("Na", 0.001), ("P", 0.001), ("S", 0.002), ("Cl", 0.003),
+                            ("K", 0.002), ("Fe", 0.001)], 75.2, 1.06)
+BREAST = _material("breast", [("H", 0.106), ("C", 0.332), ("N", 0.030), ("O", 0.527),
+                              ("Na", 0.001), ("P", 0.001), ("S", 0.002), ("Cl", 0.001)],
+                   70.3, 1.02)
+LIVER = _material("liver", [("H", 0.102), ("C", 0.139), ("N", 0.030), ("O", 0.716),
+                            ("Na", 0.002), ("P", 0.003), ("S", 0.003), ("Cl", 0.002),
+                            ("K", 0.003)], 74.7, 1.06)
+RED_MARROW = _material("red marrow", [("H", 0.105), ("C", 0.414), ("N", 0.034), ("O", 0.439),
+                                      ("P", 0.001), ("S", 0.002), ("Cl", 0.002), ("K", 0.002),
+                                      ("Fe", 0.001)], 69.9, 1.03)
+SOFT_TISSUE = _material("soft tissue", [("H", 0.101174), ("C", 0.111), ("N", 0.026),
+                                        ("O", 0.761826)], 74.9, 1.0)
+MATERIALS_16 = MATERIALS_8 + [COMPACT_BONE, SKIN, BRAIN, BLOOD, BREAST, LIVER, RED_MARROW,
+                              SOFT_TISSUE]
 
 
 def material_from_density(rho):
@@ -108,6 +135,69 @@ def eight_material_phantom(n=(40, 16, 16), h=0.5):
                                  MATERIALS_8[k]["rho_nom"]) for k in range(len(MATERIALS_8))])
     ph["materials"] = MATERIALS_8
     return ph
+
+
+def sixteen_material_phantom(n=(48, 16, 16), h=0.5):
+    """Sixteen slabs along z, one per material of MATERIALS_16 at its nominal
+    density (every table of the library present)."""
+    nz = n[0]
+    k16 = len(MATERIALS_16)
+    step = nz * h / k16
+    ph = layered_phantom(n, h, [(k * step, (k + 1) * step if k < k16 - 1 else nz * h + 1.0, k,
+                                 MATERIALS_16[k]["rho_nom"]) for k in range(k16)])
+    ph["materials"] = MATERIALS_16
+    return ph
+
+
+def ct_calibration():
+    """A synthetic CT map for the 16-material library (Schneider-type: a
+    piecewise linear HU -> density curve and HU bins that select the tissue).
+    The paper gives no numbers; these stand in for a scanner's calibration."""
+    return {"hu": [-1000.0, -800.0, -120.0, -80.0, 0.0, 60.0, 100.0, 300.0, 1000.0, 1600.0,
+                   3000.0],
+            "rho": [0.00121, 0.20, 0.93, 0.95, 1.00, 1.06, 1.09, 1.18, 1.60, 1.92, 2.80],
+            # upper bound of each bin and its library id (MATERIALS_16)
+            "upper": [-950.0, -120.0, -60.0, -20.0, 10.0, 30.0, 45.0, 55.0, 70.0, 100.0, 150.0,
+                      250.0, 300.0, 700.0, 1200.0, np.inf],
+            "material": [7, 1, 3, 12, 0, 10, 4, 11, 13, 9, 15, 5, 14, 6, 8, 2]}
+
+
+def ct_volume(shape=(160, 256, 256), h=0.2, seed=1):
+    """A synthetic CT volume (int16 HU, (z, y, x)) with the structure of a
+    patient: air around an elliptic body of soft tissue (about 40 HU) under a
+    fat layer, two lungs, a spine-like bone column (cortical shell over
+    spongiosa), organ-like ellipsoids of 30-70 HU, and 10 HU noise."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    z = (np.arange(nz) + 0.5)[:, None, None] * h
+    y = (np.arange(ny) + 0.5)[None, :, None] * h
+    x = (np.arange(nx) + 0.5)[None, None, :] * h
+    Z, Y, X = nz * h, ny * h, nx * h
+    hu = np.full(shape, -1000.0)
+    # body: ellipse in (x, z), all along y; fat within its outer 8 %
+    r_body = ((x - X / 2) / (0.45 * X)) ** 2 + ((z - Z / 2) / (0.45 * Z)) ** 2
+    body = np.broadcast_to(r_body <= 1.0, shape)
+    hu[body] = -100.0
+    inner = np.broadcast_to(r_body <= 0.85, shape)
+    hu[inner] = 40.0
+    # lungs
+    for sx in (-1, 1):
+        r = (((x - X / 2 - sx * 0.2 * X) / (0.13 * X)) ** 2 + ((y - Y * 0.45) / (0.3 * Y)) ** 2 +
+             ((z - Z * 0.45) / (0.22 * Z)) ** 2)
+        hu[np.broadcast_to(r <= 1.0, shape) & inner] = -800.0
+    # organ-like ellipsoids
+    for k in range(6):
+        c = (rng.uniform(0.3, 0.7) * X, rng.uniform(0.2, 0.8) * Y, rng.uniform(0.3, 0.7) * Z)
+        a = rng.uniform(0.04, 0.1, 3) * np.array([X, Y, Z])
+        r = ((x - c[0]) / a[0]) ** 2 + ((y - c[1]) / a[1]) ** 2 + ((z - c[2]) / a[2]) ** 2
+        sel = np.broadcast_to(r <= 1.0, shape) & inner & (hu > -500)
+        hu[sel] = rng.uniform(30.0, 70.0)
+    # spine-like column along y behind the centre: cortical shell, spongiosa core
+    rc = np.sqrt((x - X / 2) ** 2 + (z - Z * 0.72) ** 2)
+    hu[np.broadcast_to(rc <= 0.06 * X, shape)] = 1400.0
+    hu[np.broadcast_to(rc <= 0.045 * X, shape)] = 450.0
+    hu += rng.normal(0.0, 10.0, shape)
+    return np.clip(np.rint(hu), -1024, 3071).astype(np.int16)
 
 
 def slab_phantom(n=128, h=0.25):
@@ -309,6 +399,20 @@ def config(name, scale=1.0):
         ph = halfslab_phantom(256, 0.2)
         src = electron_beam(15.0, (10.0, 10.0), (25.6, 25.6), parallel=False)
         n = 100_000_000
+    elif name in ("layers8_6mv", "layers16_6mv"):
+        # one slab per library material (8 or 16 tables), 0.5 cm voxels
+        ph = (eight_material_phantom((80, 64, 64), 0.5) if name == "layers8_6mv"
+              else sixteen_material_phantom((96, 64, 64), 0.5))
+        src = photon_beam((10.0, 10.0), (16.0, 16.0), spectrum=spectrum_6mv())
+        n = 2_000_000
+    elif name == "ct_6mv":
+        # a 256 x 256 x 160 synthetic CT of 0.2 cm voxels mapped to the
+        # 16-material library on the device
+        hu = ct_volume((160, 256, 256), 0.2, seed=1)
+        ph = {"shape": hu.shape, "voxel": (0.2, 0.2, 0.2), "materials": MATERIALS_16,
+              "hu": hu, "ct_map": ct_calibration()}
+        src = photon_beam((10.0, 10.0), (25.6, 25.6), spectrum=spectrum_6mv())
+        n = 10_000_000
     elif name == "slab_6mv_psf":
         # the bench slab fed from a 2^20-record phase space of the same beam
         ph = slab_phantom(128, 0.25)
