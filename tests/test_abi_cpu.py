@@ -95,6 +95,11 @@ def test_argument_validation(omc, W):
     assert L.omc_set_params(None, None) == omc.OMC_EINVAL
     assert L.omc_run(None, 10, 1, 0, None, None) == omc.OMC_EINVAL
     assert L.omc_get_counters(None, None) == omc.OMC_EINVAL
+    assert L.omc_set_phantom_ct(None, None, 0, None) == omc.OMC_EINVAL
+    assert L.omc_get_phantom(None, None, None) == omc.OMC_EINVAL
+    # a library of more than OMC_MAX_MATERIALS (32) compositions
+    rc, _ = _create(omc, good_d, good_m, [W.WATER] * 33)
+    assert rc == omc.OMC_EINVAL
     assert L.omc_autotune(None, 1000, 1, None) == omc.OMC_EINVAL
     out = omc.SparseOut()
     out.nnz = 7  # zeroed by the call before it checks anything else
