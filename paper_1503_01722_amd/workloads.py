@@ -47,8 +47,8 @@ BONE = _material("bone", [("H", 0.034), ("C", 0.155), ("N", 0.042), ("O", 0.435)
 MATERIALS = [WATER, LUNG, BONE]   # material ids 0, 1, 2
 MAT_WATER, MAT_LUNG, MAT_BONE = 0, 1, 2
 
-# Five more ICRU-44-like compositions: with the three above, the library's
-# maximum of eight materials in one phantom (largest LDS tables).
+# Five more ICRU-44-like compositions: with the three above, eight materials,
+# the most whose tables still stage in LDS with two work-groups per CU (FP32).
 ADIPOSE = _material("adipose", [("H", 0.114), ("C", 0.598), ("N", 0.007), ("O", 0.278),
                                 ("Na", 0.001), ("S", 0.001), ("Cl", 0.001)], 63.2, 0.95)
 MUSCLE = _material("muscle", [("H", 0.102), ("C", 0.143), ("N", 0.034), ("O", 0.710),

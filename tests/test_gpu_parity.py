@@ -69,7 +69,8 @@ def _cases(W):
                     {"kerma_mode": 1})
     out["ragged_7"] = (ph, src, 7, {})
     out["single"] = (ph, src, 1, {})
-    # eight materials: the largest LDS tables (more than 64 KB per work-group)
+    # eight materials: tables of more than 64 KB per work-group (LDS in FP32,
+    # global memory in FP64)
     out["eight_materials"] = (W.eight_material_phantom(),
                               W.photon_beam((4.0, 4.0), (4.0, 4.0), spectrum=W.spectrum_6mv()),
                               3000, {})
@@ -216,7 +217,7 @@ def test_fp32_vs_fp64_build_high_statistics(omc, W, name, n):
 
 
 def test_fp32_vs_fp64_eight_materials(omc, W):
-    """The FP32 build with the largest tables (eight materials: more than 64 KB
+    """The FP32 build with large LDS tables (eight materials: more than 64 KB
     of LDS per work-group) against the FP64 build."""
     ph = W.eight_material_phantom()
     src = W.photon_beam((4.0, 4.0), (4.0, 4.0), spectrum=W.spectrum_6mv())
