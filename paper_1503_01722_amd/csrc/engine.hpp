@@ -269,12 +269,16 @@ int launch_check_records(const float* rec, uint32_t n, double ehi, uint32_t* out
 // Phantom (phantom_kernels.hip): vox[v] = {rho[v] bits, slot[mat[v]]}; and the
 // CT mapping of nvox HU values into rho and mat (library ids) with the largest
 // density bits of each material atomically raised in rmax_bits[kMaxMaterials].
-// map holds n_nodes HU nodes, n_nodes densities and n_bins bin upper bounds.
+// map holds n_nodes HU nodes, n_nodes densities, n_bins bin upper bounds and
+// n_nodes - 1 segment slopes.
 int launch_build_vox(const float* rho, const uint8_t* mat, size_t nvox, const uint32_t* slot,
                      uint32_t* vox, void* stream);
+// The mapping goes through a table of every int16 HU value (lut_rho f32 and
+// lut_mat u8, kCtLutSize entries each, indexed by HU + kCtLutSize / 2).
+constexpr int kCtLutSize = 65536;
 int launch_ct_map(const int16_t* hu, size_t nvox, const double* map, const uint32_t* bin_mat,
-                  int n_nodes, int n_bins, float* rho, uint8_t* mat, uint32_t* rmax_bits,
-                  void* stream);
+                  int n_nodes, int n_bins, float* lut_rho, uint8_t* lut_mat, float* rho,
+                  uint8_t* mat, uint32_t* rmax_bits, void* stream);
 int launch_philox_debug(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
                         uint32_t* out, void* stream);
 

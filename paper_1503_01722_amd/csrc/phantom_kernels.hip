@@ -38,63 +38,108 @@ int launch_build_vox(const float* rho, const uint8_t* mat, size_t nvox, const ui
     return status();
 }
 
-// One voxel per work-item (grid-stride). map = [hu nodes][rho nodes][bin upper
-// bounds] (FP64), bin_mat = material of each bin. Density: the end node's
-// value outside the nodes, else rho_k + (h - hu_k) * ((rho_k+1 - rho_k) /
-// (hu_k+1 - hu_k)) on the segment hu_k <= h < hu_k+1, rounded once to FP32.
-// Material: the first bin with h < upper_b, else the last. rmax_bits[m] ends
-// as the largest FP32 density bits of material m (positive floats order as
-// their bit patterns), reduced per work-group in LDS first.
+// The CT mapping, in two launches. ct_lut_kernel evaluates the mapping once
+// for each of the 65536 int16 HU values: map = [hu nodes][rho nodes][bin upper
+// bounds][segment slopes (rho_k+1 - rho_k) / (hu_k+1 - hu_k), divided on the
+// host: the same correctly rounded FP64 quotient the definition takes] and
+// bin_mat = the material of each bin. Density: the end node's value outside
+// the nodes, else rho_k + (h - hu_k) * slope_k on the segment hu_k <= h <
+// hu_k+1, rounded once to FP32. Material: the first bin with h < upper_b, else
+// the last. ct_map_kernel then maps every voxel by a lookup in that table
+// (320 KB, L2-resident): one coalesced 2-byte read and 5 bytes written per
+// voxel.
 __global__ void __launch_bounds__(256)
-ct_map_kernel(const int16_t* __restrict__ hu, size_t nvox, const double* __restrict__ map,
-              const uint32_t* __restrict__ bin_mat, int n_nodes, int n_bins,
-              float* __restrict__ rho, uint8_t* __restrict__ mat, uint32_t* __restrict__ rmax_bits)
+ct_lut_kernel(const double* __restrict__ map, const uint32_t* __restrict__ bin_mat, int n_nodes,
+              int n_bins, float* __restrict__ lut_rho, uint8_t* __restrict__ lut_mat)
 {
-    __shared__ double s_map[2 * kMaxCtNodes + kMaxCtBins];
-    __shared__ uint32_t s_mat[kMaxCtBins];
+    const int i = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (i >= kCtLutSize) return;
+    const double* H = map;
+    const double* P = map + n_nodes;
+    const double* U = map + 2 * n_nodes;
+    const double* S = map + 2 * n_nodes + n_bins;
+    const double h = double(i - kCtLutSize / 2);
+    double r;
+    if (h <= H[0]) {
+        r = P[0];
+    } else if (h >= H[n_nodes - 1]) {
+        r = P[n_nodes - 1];
+    } else {
+        int j = 0;
+        while (j + 2 < n_nodes && H[j + 1] <= h) ++j;
+        r = P[j] + (h - H[j]) * S[j];
+    }
+    int b = 0;
+    while (b + 1 < n_bins && !(h < U[b])) ++b;
+    lut_rho[i] = float(r);
+    lut_mat[i] = uint8_t(bin_mat[b]);
+}
+
+// rmax_bits[m] ends as the largest FP32 density bits of material m (positive
+// floats order as their bit patterns). Each work-item walks a column of
+// kCtRun voxels 256 apart (coalesced across the work-group) and keeps the
+// running maximum of its current material, so that the LDS maximum is taken
+// when the material changes rather than once per voxel.
+constexpr int kCtRun = 16;
+
+__global__ void __launch_bounds__(256)
+ct_map_kernel(const int16_t* __restrict__ hu, size_t nvox, const float* __restrict__ lut_rho,
+              const uint8_t* __restrict__ lut_mat, float* __restrict__ rho,
+              uint8_t* __restrict__ mat, uint32_t* __restrict__ rmax_bits)
+{
     __shared__ uint32_t s_max[kMaxMaterials];
-    const int n_map = 2 * n_nodes + n_bins;
-    for (int k = threadIdx.x; k < n_map; k += 256) s_map[k] = map[k];
-    for (int k = threadIdx.x; k < n_bins; k += 256) s_mat[k] = bin_mat[k];
     for (int k = threadIdx.x; k < kMaxMaterials; k += 256) s_max[k] = 0u;
     __syncthreads();
-    const double* H = s_map;
-    const double* P = s_map + n_nodes;
-    const double* U = s_map + 2 * n_nodes;
-    for (size_t v = size_t(blockIdx.x) * 256 + threadIdx.x; v < nvox;
-         v += size_t(gridDim.x) * 256) {
-        const double h = double(hu[v]);
-        double r;
-        if (h <= H[0]) {
-            r = P[0];
-        } else if (h >= H[n_nodes - 1]) {
-            r = P[n_nodes - 1];
-        } else {
-            int k = 0;
-            while (k + 2 < n_nodes && H[k + 1] <= h) ++k;
-            const double slope = (P[k + 1] - P[k]) / (H[k + 1] - H[k]);
-            r = P[k] + (h - H[k]) * slope;
-        }
-        int b = 0;
-        while (b + 1 < n_bins && !(h < U[b])) ++b;
-        const float rf = float(r);
-        const uint32_t m = s_mat[b];
+    uint32_t cur_m = 0, cur_max = 0;
+    auto one = [&](size_t v, int h) {
+        const int i = h + kCtLutSize / 2;
+        const float rf = lut_rho[i];
+        const uint32_t m = lut_mat[i];
         rho[v] = rf;
         mat[v] = uint8_t(m);
-        atomicMax(&s_max[m], __float_as_uint(rf));
+        const uint32_t bits = __float_as_uint(rf);
+        if (m == cur_m) {
+            cur_max = bits > cur_max ? bits : cur_max;
+        } else {
+            if (cur_max) atomicMax(&s_max[cur_m], cur_max);
+            cur_m = m;
+            cur_max = bits;
+        }
+    };
+    const size_t stride = size_t(gridDim.x) * 256 * kCtRun;
+    for (size_t t0 = size_t(blockIdx.x) * 256 * kCtRun; t0 < nvox; t0 += stride) {
+        if (t0 + size_t(256) * kCtRun <= nvox) {
+            // a whole tile: all its HU loads in flight before the first lookup
+            int hv[kCtRun];
+#pragma unroll
+            for (int k = 0; k < kCtRun; ++k) hv[k] = hu[t0 + size_t(k) * 256 + threadIdx.x];
+#pragma unroll
+            for (int k = 0; k < kCtRun; ++k) one(t0 + size_t(k) * 256 + threadIdx.x, hv[k]);
+        } else {
+            for (int k = 0; k < kCtRun; ++k) {
+                const size_t v = t0 + size_t(k) * 256 + threadIdx.x;
+                if (v >= nvox) break;
+                one(v, hu[v]);
+            }
+        }
     }
+    if (cur_max) atomicMax(&s_max[cur_m], cur_max);
     __syncthreads();
     for (int k = threadIdx.x; k < kMaxMaterials; k += 256)
         if (s_max[k]) atomicMax(&rmax_bits[k], s_max[k]);
 }
 
 int launch_ct_map(const int16_t* hu, size_t nvox, const double* map, const uint32_t* bin_mat,
-                  int n_nodes, int n_bins, float* rho, uint8_t* mat, uint32_t* rmax_bits,
-                  void* stream)
+                  int n_nodes, int n_bins, float* lut_rho, uint8_t* lut_mat, float* rho,
+                  uint8_t* mat, uint32_t* rmax_bits, void* stream)
 {
-    const size_t blocks = std::min<size_t>((nvox + 255) / 256, 16384);
+    hipLaunchKernelGGL(ct_lut_kernel, dim3(kCtLutSize / 256), dim3(256), 0, (hipStream_t)stream,
+                       map, bin_mat, n_nodes, n_bins, lut_rho, lut_mat);
+    if (status()) return -1;
+    const size_t per = size_t(256) * kCtRun;
+    const size_t blocks = std::min<size_t>((nvox + per - 1) / per, 16384);
     hipLaunchKernelGGL(ct_map_kernel, dim3(unsigned(blocks)), dim3(256), 0, (hipStream_t)stream,
-                       hu, nvox, map, bin_mat, n_nodes, n_bins, rho, mat, rmax_bits);
+                       hu, nvox, lut_rho, lut_mat, rho, mat, rmax_bits);
     return status();
 }
 

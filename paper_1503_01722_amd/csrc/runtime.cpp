@@ -1520,17 +1520,23 @@ int omc_set_phantom_ct(omc_ctx* c, const int16_t* hu, int hu_on_device, const om
         return fail(c, OMC_EINVAL, "hu_on_device: the HU values must be an allocation of this "
                                    "context's device holding nx * ny * nz int16 values");
     // map [hu][rho][upper], bin materials, per-material maxima, and host HU
-    std::vector<double> m(size_t(2 * nn + nb), 0.0);
+    // [hu][rho][upper][slopes]: the segment slopes are the definition's FP64
+    // quotients, taken once here instead of per voxel
+    std::vector<double> m(size_t(3 * nn - 1 + nb), 0.0);
     for (int k = 0; k < nn; ++k) {
         m[k] = map->hu[k];
         m[nn + k] = map->rho[k];
     }
     for (int b = 0; b + 1 < nb; ++b) m[2 * nn + b] = map->hu_upper[b];
+    for (int k = 0; k + 1 < nn; ++k)
+        m[2 * nn + nb + k] = (map->rho[k + 1] - map->rho[k]) / (map->hu[k + 1] - map->hu[k]);
     std::vector<uint32_t> bm(nb);
     for (int b = 0; b < nb; ++b) bm[b] = uint32_t(map->material[b]);
     const size_t o_mat = align256(m.size() * sizeof(double));
     const size_t o_max = o_mat + align256(bm.size() * sizeof(uint32_t));
-    const size_t o_hu = o_max + align256(omc::kMaxMaterials * sizeof(uint32_t));
+    const size_t o_lr = o_max + align256(omc::kMaxMaterials * sizeof(uint32_t));
+    const size_t o_lm = o_lr + align256(omc::kCtLutSize * sizeof(float));
+    const size_t o_hu = o_lm + align256(omc::kCtLutSize * sizeof(uint8_t));
     const size_t total = o_hu + (hu_on_device ? 0 : c->nvox * sizeof(int16_t));
     char* buf = nullptr;
     if (hipMalloc(&buf, total) != hipSuccess) return fail(c, OMC_ENOMEM, "hipMalloc failed for the CT map");
@@ -1548,8 +1554,10 @@ int omc_set_phantom_ct(omc_ctx* c, const int16_t* hu, int hu_on_device, const om
         d_hu = reinterpret_cast<const int16_t*>(buf + o_hu);
     }
     if (omc::launch_ct_map(d_hu, c->nvox, reinterpret_cast<const double*>(buf),
-                           reinterpret_cast<const uint32_t*>(buf + o_mat), nn, nb, c->d_rho,
-                           c->d_mat, reinterpret_cast<uint32_t*>(buf + o_max), nullptr))
+                           reinterpret_cast<const uint32_t*>(buf + o_mat), nn, nb,
+                           reinterpret_cast<float*>(buf + o_lr),
+                           reinterpret_cast<uint8_t*>(buf + o_lm), c->d_rho, c->d_mat,
+                           reinterpret_cast<uint32_t*>(buf + o_max), nullptr))
         return fail(c, OMC_EDEVICE, "CT mapping launch failed");
     uint32_t mx[omc::kMaxMaterials];
     HIP_TRY(c, hipMemcpy(mx, buf + o_max, sizeof mx, hipMemcpyDeviceToHost));
