@@ -229,3 +229,38 @@ def test_ct_mapping_errors_leave_the_phantom(omc, W):
     after = eng.get_phantom()
     eng.close()
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+
+
+def test_fp64_library_graph_beamlets_and_phantom_swap(omc, orc, W):
+    """One context on the 16-material library: graph mode with tables in global
+    memory, beamlets, then a new phantom with another set of materials (new
+    slots, new tables, a new capture) - each against the oracle."""
+    ph16 = W.sixteen_material_phantom()
+    src = W.photon_beam((4.0, 4.0), (4.0, 4.0), spectrum=W.spectrum_6mv())
+    eng = omc.Engine(ph16)
+    eng.set_source(src)
+    eng.set_params(parity_fp64=1, graph_depth=2, chunk_histories=1000)
+    eng.run(2500, seed=8)
+    c = eng.counters()
+    _, _, oc = orc.run(ph16, src, 2500, seed=8)
+    assert ints(c) == ints(oc)
+    allb = [(src, 700, 0), (W.photon_beam((2.0, 2.0), (3.0, 5.0), mono_E=3.0), 400, 700)]
+    sp = eng.run_beamlets(allb, seed=9)
+    cb = eng.counters()
+    od, ocb = orc.run_beamlets(ph16, allb, seed=9)
+    assert ints(cb) == ints(ocb)
+    nvox = int(np.prod(ph16["shape"]))
+    for b, ref in enumerate(od):
+        g = sp.row(b, nvox).reshape(ph16["shape"])
+        np.testing.assert_allclose(g, ref, rtol=2e-6, atol=1e-9 * max(ref.max(), 1e-300))
+    # the same dimensions, three other library materials
+    sp_ph = W.layered_phantom(ph16["shape"], 0.5, [(0.0, 8.0, 9, 1.09), (8.0, 14.0, 14, 1.03),
+                                                   (14.0, 25.0, 2, 1.85)])
+    sp_ph["materials"] = W.MATERIALS_16
+    eng.set_phantom(sp_ph)
+    d, _ = eng.run(2500, seed=10)
+    c2 = eng.counters()
+    eng.close()
+    od2, _, oc2 = orc.run(sp_ph, src, 2500, seed=10)
+    assert ints(c2) == ints(oc2)
+    np.testing.assert_allclose(d, od2, rtol=1e-6, atol=1e-9 * od2.max())
