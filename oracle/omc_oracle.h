@@ -105,6 +105,10 @@ typedef struct {
      * psf (8 floats: E, x, y, z, u, v, w, unused) */
     int n_psf;
     const float* psf;
+    /* photon flights: 0 Woodcock with the phantom majorant (Sec. 2.1); 1 with
+     * a majorant per macro cell (the cure for the fictitious interactions
+     * Sec. 3.2 reports in heterogeneous phantoms), see woodcock_cells */
+    int photon_mode;
 } orc_problem;
 
 /* --- random numbers (Philox4x32-10, Salmon et al. SC'11) ------------------ */

@@ -75,7 +75,8 @@ class Problem(C.Structure):
                 ("Eabs_e", C.c_double), ("Eabs_g", C.c_double), ("Wcc", C.c_double),
                 ("kc", C.c_double), ("dmax_s", C.c_double), ("f_E", C.c_double),
                 ("n_batches", C.c_int), ("kerma_mode", C.c_int), ("csda_mode", C.c_int),
-                ("electron_mode", C.c_int), ("n_psf", C.c_int), ("psf", C.POINTER(C.c_float))]
+                ("electron_mode", C.c_int), ("n_psf", C.c_int), ("psf", C.POINTER(C.c_float)),
+                ("photon_mode", C.c_int)]
 
 
 _lib = None
@@ -210,7 +211,7 @@ def node_energies():
 # --- problems ------------------------------------------------------------------------------
 
 DEFAULT_PARAMS = dict(Eabs_e=0.2, Eabs_g=0.05, Wcc=0.05, kc=0.2, dmax_s=0.5, f_E=0.25,
-                      n_batches=10, kerma_mode=0, csda_mode=0, electron_mode=0)
+                      n_batches=10, kerma_mode=0, csda_mode=0, electron_mode=0, photon_mode=0)
 
 
 class _ProblemHolder:
@@ -244,7 +245,7 @@ class _ProblemHolder:
             p["Eabs_e"], p["Eabs_g"], p["Wcc"], p["kc"], p["dmax_s"], p["f_E"],
             int(p["n_batches"]), int(p["kerma_mode"]), int(p["csda_mode"]),
             int(p["electron_mode"]), int(self.psf.shape[0]) if psf is not None else 0,
-            self.psf.ctypes.data_as(C.POINTER(C.c_float)))
+            self.psf.ctypes.data_as(C.POINTER(C.c_float)), int(p["photon_mode"]))
 
 
 def run(phantom, source, n, seed=1, h0=0, params=None, threads=None):

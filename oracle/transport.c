@@ -112,6 +112,11 @@ typedef struct {
     double log2A[ORC_NA];
     double* cdf;
     double skin; /* boundary skin depth, cm */
+    /* macro cells of 2^cshift voxels per side (photon_mode 1): cn cells per
+     * axis and the majorant scale q of each cell in 255ths */
+    int cshift;
+    int cn[3];
+    unsigned char* cellq;
 } ctx_t;
 
 typedef struct {
@@ -328,6 +333,78 @@ static int woodcock(const ctx_t* C, part_t* p, tally_t* t, size_t* vout, int* io
     }
 }
 
+/* The same flights with a majorant per macro cell (photon_mode 1): the
+ * optical depth tau = -ln u is spent cell by cell, mu_c = mu_hat * q_c / 255
+ * in cell c, the path crossing each cell face (snapped onto it, the cell
+ * index stepped); the candidate is accepted with rho mu / mu_c. Leaving the
+ * cell grid or the box is an escape. Ties between faces go to the lower axis. */
+static int woodcock_cells(const ctx_t* C, part_t* p, tally_t* t, size_t* vout, int* iout,
+                          double* fout)
+{
+    int i;
+    double f;
+    orc__grid_pos(p->E, &i, &f);
+    const double mh = lerp(C->muhat, i, f);
+    const int S = C->cshift;
+    const double W[3] = {(double)(1 << S) * C->h[0], (double)(1 << S) * C->h[1],
+                         (double)(1 << S) * C->h[2]};
+    const int maxn = C->cn[0] + C->cn[1] + C->cn[2] + 2;
+    for (;;) {
+        double tau = -log(rng_u(&p->rng));
+        t->c.ph_flights++;
+        int c[3] = {p->iv[0] >> S, p->iv[1] >> S, p->iv[2] >> S};
+        double mc = mh;
+        int inside = 0;
+        for (int n = 0; n < maxn; ++n) {
+            const int q = C->cellq[c[0] + C->cn[0] * (c[1] + C->cn[1] * c[2])];
+            mc = q == 255 ? mh : (mh * (double)q) / 255.0;
+            double d = INFINITY;
+            int ax = 0;
+            for (int a = 0; a < 3; ++a) {
+                double ta;
+                if (p->d[a] > 0.0)
+                    ta = ((double)(c[a] + 1) * W[a] - p->x[a]) / p->d[a];
+                else if (p->d[a] < 0.0)
+                    ta = ((double)c[a] * W[a] - p->x[a]) / p->d[a];
+                else
+                    continue;
+                if (ta < d) {
+                    d = ta;
+                    ax = a;
+                }
+            }
+            if (d < 0.0) d = 0.0;
+            if (tau < mc * d) {
+                const double s = tau / mc;
+                for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + s * p->d[a];
+                inside = 1;
+                break;
+            }
+            tau = tau - mc * d;
+            for (int a = 0; a < 3; ++a) p->x[a] = p->x[a] + d * p->d[a];
+            const int up = p->d[ax] > 0.0;
+            p->x[ax] = (double)(c[ax] + up) * W[ax];
+            c[ax] += up ? 1 : -1;
+            if (c[ax] < 0 || c[ax] >= C->cn[ax]) break;
+        }
+        if (!inside || !locate(C, p->x, p->iv)) {
+            t->c.E_escaped += p->E;
+            t->c.ph_escaped++;
+            return 0;
+        }
+        const size_t v = lin(C, p->iv);
+        const orc_mat_tables* T = &C->tab[C->P->mat[v]];
+        const double mt = lerp(T->muTot, i, f);
+        if (rng_u(&p->rng) * mc < C->rho[v] * mt) {
+            *vout = v;
+            *iout = i;
+            *fout = f;
+            return 1;
+        }
+        t->c.ph_fictitious++;
+    }
+}
+
 /* Interaction type at a real event: 1 Compton, 2 photoelectric, 3 pair.
  * Below the pair threshold the pair interval counts as absorption. */
 static int select_type(const ctx_t* C, part_t* p, size_t v, int i, double f)
@@ -390,7 +467,9 @@ static void transport_photon(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
         size_t v;
         int i;
         double f;
-        if (!woodcock(C, p, t, &v, &i, &f)) return;
+        const int real = C->P->photon_mode == 1 ? woodcock_cells(C, p, t, &v, &i, &f)
+                                                 : woodcock(C, p, t, &v, &i, &f);
+        if (!real) return;
         const int type = select_type(C, p, v, i, f);
         if (type == 1) {
             compton(C, p, st, t);
@@ -880,6 +959,43 @@ static int ctx_init(ctx_t* C, const orc_problem* P, uint32_t seed)
         C->muhat[i] = mx;
     }
     free(rmax);
+    /* macro cells: the smallest power-of-two side that leaves at most 4096 */
+    C->cshift = 0;
+    for (;;) {
+        size_t nc = 1;
+        for (int a = 0; a < 3; ++a) {
+            C->cn[a] = (C->n[a] + (1 << C->cshift) - 1) >> C->cshift;
+            nc *= (size_t)C->cn[a];
+        }
+        if (nc <= 4096) break;
+        C->cshift += 1;
+    }
+    C->cellq = (unsigned char*)calloc((size_t)C->cn[0] * C->cn[1] * C->cn[2], 1);
+    if (P->photon_mode == 1) {
+        /* r_m: the largest ratio of material m's attenuation to the majorant
+         * over the energy nodes; a voxel of density rho needs the scale
+         * rho * r_m, and its cell takes the largest, rounded up to 255ths */
+        double* r = (double*)calloc((size_t)P->n_mats, sizeof(double));
+        for (int m = 0; m < P->n_mats; ++m)
+            for (int i = 0; i < ORC_NE; ++i) {
+                const double q = C->tab[m].muTot[i] / C->muhat[i];
+                if (C->muhat[i] > 0.0 && q > r[m]) r[m] = q;
+            }
+        for (int z = 0; z < C->n[2]; ++z)
+            for (int y = 0; y < C->n[1]; ++y)
+                for (int x = 0; x < C->n[0]; ++x) {
+                    const int iv[3] = {x, y, z};
+                    const size_t v = lin(C, iv);
+                    double qd = ceil(255.0 * (C->rho[v] * r[P->mat[v]]));
+                    if (qd < 1.0) qd = 1.0;
+                    if (qd > 255.0) qd = 255.0;
+                    const size_t c = (size_t)(x >> C->cshift) +
+                                     (size_t)C->cn[0] * ((size_t)(y >> C->cshift) +
+                                                         (size_t)C->cn[1] * (size_t)(z >> C->cshift));
+                    if ((unsigned char)qd > C->cellq[c]) C->cellq[c] = (unsigned char)qd;
+                }
+        free(r);
+    }
     orc_build_ms_table(C->log2A);
     if (P->n_bins > 0) {
         C->cdf = (double*)malloc((size_t)P->n_bins * sizeof(double));
@@ -899,6 +1015,7 @@ static void ctx_free(ctx_t* C)
     free(C->tab);
     free(C->Rabs);
     free(C->cdf);
+    free(C->cellq);
 }
 
 static void counters_add(orc_counters* a, const orc_counters* b)
@@ -1034,7 +1151,9 @@ int orc_first_interaction(const orc_problem* P, uint32_t seed, uint32_t h0, uint
         size_t v;
         int i;
         double f;
-        if (woodcock(&C, &p, &t, &v, &i, &f)) type[k] = select_type(&C, &p, v, i, f);
+        const int real = P->photon_mode == 1 ? woodcock_cells(&C, &p, &t, &v, &i, &f)
+                                             : woodcock(&C, &p, &t, &v, &i, &f);
+        if (real) type[k] = select_type(&C, &p, v, i, f);
         for (int a = 0; a < 3; ++a) pos[3 * k + a] = p.x[a];
     }
     *n_fict = t.c.ph_fictitious;

@@ -51,11 +51,15 @@ def test_narrow_beam_attenuation_water(orc, W, E):
     assert np.all(pos[typ == 0, 2] >= 16.0)
 
 
-def test_narrow_beam_attenuation_slab(orc, W):
+@pytest.mark.parametrize("photon_mode", [0, 1])
+def test_narrow_beam_attenuation_slab(orc, W, photon_mode):
+    """exp(-integral of mu) through the slab's layers, with the phantom majorant
+    and with a majorant per macro cell (the optical depth spent cell by cell)."""
     ph = W.slab_phantom(64, 0.5)
     E = 2.0
     n = 100_000
-    pos, typ, nfict = orc.first_interaction(ph, pencil_photons(W, E, (16.0, 16.0)), n, seed=8)
+    pos, typ, nfict = orc.first_interaction(ph, pencil_photons(W, E, (16.0, 16.0)), n, seed=8,
+                                            params={"photon_mode": photon_mode})
     assert nfict > 0  # majorant is bone: fictitious events in water and lung
     mus = {m: lookup(orc, orc.mat_tables(M)["muTot"], E) for m, M in enumerate(W.MATERIALS)}
     layers = [(0, 2, 1.0 * mus[0]), (2, 4, 1.85 * mus[2]), (4, 10, 0.26 * mus[1]),
@@ -384,3 +388,34 @@ def test_phase_space_ledger_6mv(orc, W):
     assert ledger_ok(c)
     assert 0 < c["src_miss"] < 0.05 * n
     bookkeeping(c, n - c["src_miss"], 0)
+
+
+# --- photon majorant per macro cell (photon_mode 1) ---------------------------------------
+
+def test_cell_majorants_same_dose_fewer_fictitious(orc, W):
+    """Majorants per macro cell change how flights are sampled, not what is
+    simulated: the same real-event rates and dose as the phantom majorant
+    (independent runs, statistically), with most fictitious events gone."""
+    from parity import dose_agreement
+    ph = W.slab_phantom(64, 0.5)
+    src = W.photon_beam((10.0, 10.0), (16.0, 16.0), spectrum=W.spectrum_6mv())
+    n = 200_000
+    a, a2, ca = orc.run(ph, src, n, seed=1, threads=8, params={"photon_mode": 0})
+    b, b2, cb = orc.run(ph, src, n, seed=2, threads=8, params={"photon_mode": 1})
+    ref, _, _ = orc.run(ph, src, n, seed=3, threads=8, params={"photon_mode": 1})
+    assert ledger_ok(cb)
+    assert cb["ph_fictitious"] < 0.2 * ca["ph_fictitious"]
+    for k in ("ph_compton", "el_steps"):
+        ra, rb = ca[k] / n, cb[k] / n
+        assert abs(ra - rb) < 0.01 * ra, k
+    agr = dose_agreement(a, a2, b, b2, ref)
+    assert agr["within2s"] > 0.9 and abs(agr["bias"]) < 0.003
+
+
+def test_cell_majorants_homogeneous_phantom(orc, W):
+    """In a uniform phantom every cell scale is the full majorant: no fictitious
+    events in either mode."""
+    ph = W.water_phantom((32, 32, 32), 0.5)
+    src = W.photon_beam((4.0, 4.0), (8.0, 8.0), mono_E=2.0, parallel=True)
+    _, _, c = orc.run(ph, src, 20_000, seed=4, threads=4, params={"photon_mode": 1})
+    assert c["ph_fictitious"] == 0 and c["ph_flights"] > 0
