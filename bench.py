@@ -254,6 +254,9 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--straggler-lanes", type=int, default=-1)
+    ap.add_argument("--photon-mode", type=int, default=0,
+                    help="0: Woodcock flights with the phantom majorant (the method); 1: with "
+                         "a majorant per macro cell")
     ap.add_argument("--table-mode", type=int, default=0,
                     help="per-material tables: 0 LDS while two work-groups fit a CU with "
                          "them, else global memory; 1 LDS; 2 global memory")
@@ -320,6 +323,8 @@ def main():
         shape["electron_mode"] = args.electron_mode
     if args.table_mode:
         shape["table_mode"] = args.table_mode
+    if args.photon_mode:
+        shape["photon_mode"] = args.photon_mode
     eng = omc.Engine(ph)
     eng.set_source(src)
     eng.set_params(parity_fp64=int(args.parity_fp64), **shape)
@@ -372,6 +377,8 @@ def main():
                       "electron_steps": ("fixed, across voxels" if params["electron_mode"]
                                          else "voxel-limited"),
                       "material_tables": tables,
+                      "photon_flights": ("majorant per macro cell" if params["photon_mode"]
+                                         else "phantom majorant"),
                       "launch": {k: params[k] for k in ("block_size", "blocks_per_cu",
                                                         "chunk_histories", "graph_depth",
                                                         "queue_factor", "straggler_lanes")}}}

@@ -151,6 +151,15 @@ typedef struct {
                                 OMC_EUNSUP when they exceed a work-group's LDS); 2 in global
                                 memory, through L2; 0 LDS while two work-groups still fit a
                                 CU with them, else global (0). Results do not depend on it */
+    int photon_mode;         /* 0: Woodcock flights with the phantom's majorant (Sec. 2.1);
+                                1: with a majorant per macro cell, the remedy for the many
+                                fictitious interactions Sec. 3.2 reports in heterogeneous
+                                phantoms: cells of 2^k voxels per side (the smallest k that
+                                leaves at most 4096 cells), each with the largest over its
+                                voxels of rho times the material's largest ratio to the
+                                majorant over the energy nodes, rounded up to 255ths; a
+                                flight spends its optical depth -ln u cell by cell, and a
+                                candidate is accepted with rho mu / mu_cell (0) */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */

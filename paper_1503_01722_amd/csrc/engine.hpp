@@ -182,9 +182,19 @@ struct TraceView {
 };
 constexpr int kTraceWords = 12;
 
+// Macro cells of 2^shift voxels per side for the photon majorant per cell:
+// q[cell] (cells x fastest, at most kMaxCells) is the cell's majorant scale
+// in 255ths of the phantom majorant.
+constexpr int kMaxCells = 4096;
+struct CellView {
+    const uint32_t* q;
+    int nx, ny, nz, shift;
+};
+
 template <typename R>
 struct KernelArgs {
     PhantomView<R> ph;
+    CellView cell;
     TableView<R> tab;
     ParamView<R> prm;
     QueueView<R> qin;     // consumed by a transport kernel
@@ -205,10 +215,12 @@ struct KernelArgs {
 // LDS bytes a transport work-group stages: the tables of every material the
 // phantom holds, or (gtab: the per-material tables read from global memory,
 // through L2) only the photon majorant, the scattering table and R(E_abs).
+// (cells: the cell scales staged too, one byte each, for photon_mode 1)
 template <typename R>
-inline size_t photon_lds_bytes(int n_mats, bool gtab = false)
+inline size_t photon_lds_bytes(int n_mats, bool gtab = false, int cells = 0)
 {
-    return (gtab ? 0 : 4 * sizeof(R) * size_t(n_mats) * kTabNE) + sizeof(R) * kTabNE;
+    return (gtab ? 0 : 4 * sizeof(R) * size_t(n_mats) * kTabNE) + sizeof(R) * kTabNE +
+           ((size_t(cells) + 15) & ~size_t(15));
 }
 template <typename R>
 inline size_t electron_lds_bytes(int n_mats, bool gtab = false)
@@ -224,8 +236,9 @@ template <typename R>
 struct Launch {
     static int prepare(size_t lds_ph, size_t lds_el, bool gtab);
     static int source(const KernelArgs<R>& a, int grid, int block, void* stream);
+    // cells: flights with a majorant per macro cell (photon_mode 1)
     static int photon(const KernelArgs<R>& a, int grid, int block, size_t lds, bool gtab,
-                      void* stream);
+                      bool cells, void* stream);
     // fixed: steps across voxels (electron_mode 1), a kernel of its own
     static int electron(const KernelArgs<R>& a, int grid, int block, size_t lds, bool fixed,
                         bool gtab, void* stream);
@@ -273,6 +286,11 @@ int launch_check_records(const float* rec, uint32_t n, double ehi, uint32_t* out
 // n_nodes - 1 segment slopes.
 int launch_build_vox(const float* rho, const uint8_t* mat, size_t nvox, const uint32_t* slot,
                      uint32_t* vox, void* stream);
+// Cell scales: q[cell] = max over its voxels of min(255, max(1, ceil(255 *
+// (rho * r[slot])))), r[slot] the largest ratio of the material's attenuation
+// to the phantom majorant over the energy nodes (q zeroed before).
+int launch_cell_scales(const uint32_t* vox, int nx, int ny, int nz, int shift, int cnx, int cny,
+                       const double* r, uint32_t* q, void* stream);
 // The mapping goes through a table of every int16 HU value (lut_rho f32 and
 // lut_mat u8, kCtLutSize entries each, indexed by HU + kCtLutSize / 2).
 constexpr int kCtLutSize = 65536;

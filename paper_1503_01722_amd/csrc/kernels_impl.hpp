@@ -30,12 +30,14 @@ int Launch<R>::prepare(size_t lds_ph, size_t lds_el, bool gtab)
                                                   int(lds)) != hipSuccess;
     };
     if (gtab)
-        return raise((const void*)photon_kernel<R, true>, lds_ph) ||
+        return raise((const void*)photon_kernel<R, true, false>, lds_ph) ||
+                       raise((const void*)photon_kernel<R, true, true>, lds_ph) ||
                        raise((const void*)electron_kernel<R, false, true>, lds_el) ||
                        raise((const void*)electron_kernel<R, true, true>, lds_el)
                    ? -1
                    : 0;
-    return raise((const void*)photon_kernel<R, false>, lds_ph) ||
+    return raise((const void*)photon_kernel<R, false, false>, lds_ph) ||
+                   raise((const void*)photon_kernel<R, false, true>, lds_ph) ||
                    raise((const void*)electron_kernel<R, false, false>, lds_el) ||
                    raise((const void*)electron_kernel<R, true, false>, lds_el)
                ? -1
@@ -44,14 +46,17 @@ int Launch<R>::prepare(size_t lds_ph, size_t lds_el, bool gtab)
 
 template <typename R>
 int Launch<R>::photon(const KernelArgs<R>& a, int grid, int block, size_t lds, bool gtab,
-                      void* stream)
+                      bool cells, void* stream)
 {
-    if (gtab)
-        hipLaunchKernelGGL((photon_kernel<R, true>), dim3(grid), dim3(block), lds,
-                           (hipStream_t)stream, a);
+    const hipStream_t s = (hipStream_t)stream;
+    if (gtab && cells)
+        hipLaunchKernelGGL((photon_kernel<R, true, true>), dim3(grid), dim3(block), lds, s, a);
+    else if (gtab)
+        hipLaunchKernelGGL((photon_kernel<R, true, false>), dim3(grid), dim3(block), lds, s, a);
+    else if (cells)
+        hipLaunchKernelGGL((photon_kernel<R, false, true>), dim3(grid), dim3(block), lds, s, a);
     else
-        hipLaunchKernelGGL((photon_kernel<R, false>), dim3(grid), dim3(block), lds,
-                           (hipStream_t)stream, a);
+        hipLaunchKernelGGL((photon_kernel<R, false, false>), dim3(grid), dim3(block), lds, s, a);
     return detail::launch_status();
 }
 

@@ -38,6 +38,35 @@ int launch_build_vox(const float* rho, const uint8_t* mat, size_t nvox, const ui
     return status();
 }
 
+__global__ void __launch_bounds__(256)
+cell_scale_kernel(const uint2* __restrict__ vox, int nx, int ny, int nz, int shift, int cnx,
+                  int cny, const double* __restrict__ r, uint32_t* __restrict__ q)
+{
+    const size_t nvox = size_t(nx) * size_t(ny) * size_t(nz);
+    for (size_t v = size_t(blockIdx.x) * 256 + threadIdx.x; v < nvox;
+         v += size_t(gridDim.x) * 256) {
+        const uint2 rec = vox[v];
+        double qd = ceil(255.0 * (double(__uint_as_float(rec.x)) * r[rec.y]));
+        qd = qd < 1.0 ? 1.0 : (qd > 255.0 ? 255.0 : qd);
+        const int x = int(v % size_t(nx));
+        const int y = int((v / size_t(nx)) % size_t(ny));
+        const int z = int(v / (size_t(nx) * size_t(ny)));
+        const int c = (x >> shift) + cnx * ((y >> shift) + cny * (z >> shift));
+        atomicMax(&q[c], uint32_t(qd));
+    }
+}
+
+int launch_cell_scales(const uint32_t* vox, int nx, int ny, int nz, int shift, int cnx, int cny,
+                       const double* r, uint32_t* q, void* stream)
+{
+    const size_t nvox = size_t(nx) * size_t(ny) * size_t(nz);
+    const size_t blocks = std::min<size_t>((nvox + 255) / 256, 16384);
+    hipLaunchKernelGGL(cell_scale_kernel, dim3(unsigned(blocks)), dim3(256), 0,
+                       (hipStream_t)stream, reinterpret_cast<const uint2*>(vox), nx, ny, nz,
+                       shift, cnx, cny, r, q);
+    return status();
+}
+
 // The CT mapping, in two launches. ct_lut_kernel evaluates the mapping once
 // for each of the 65536 int16 HU values: map = [hu nodes][rho nodes][bin upper
 // bounds][segment slopes (rho_k+1 - rho_k) / (hu_k+1 - hu_k), divided on the

@@ -51,6 +51,10 @@ struct DeviceTables {
     R* Rabs = nullptr;
     R* edges = nullptr;
     uint32_t rshift = 0, rbase = 0, rcells = 1;
+    // macro-cell majorant scales (photon_mode 1), built with the tables
+    uint32_t* cellq = nullptr;
+    double* cell_r = nullptr;
+    int cnx = 1, cny = 1, cnz = 1, cshift = 0;
     bool valid = false;
 };
 
@@ -177,6 +181,8 @@ void free_tables(DeviceTables<R>& t)
     dfree(t.Rabs);
     dfree(t.edges);
     t.valid = false;
+    dfree(t.cellq);
+    dfree(t.cell_r);
 }
 
 template <typename R>
@@ -287,6 +293,50 @@ void range_index(const std::vector<R>& rtab, int nm, DeviceTables<R>& t,
     }
 }
 
+// Macro cells for the photon majorant per cell (photon_mode 1): the smallest
+// power-of-two side that leaves at most kMaxCells cells; each cell's scale is
+// the largest over its voxels of rho * r_m in 255ths, rounded up, r_m the
+// largest ratio of material m's attenuation to the majorant over the nodes.
+template <typename R>
+int cell_scales(omc_ctx* c, DeviceTables<R>& t)
+{
+    t.cshift = 0;
+    for (;;) {
+        t.cnx = (c->nx + (1 << t.cshift) - 1) >> t.cshift;
+        t.cny = (c->ny + (1 << t.cshift) - 1) >> t.cshift;
+        t.cnz = (c->nz + (1 << t.cshift) - 1) >> t.cshift;
+        if (size_t(t.cnx) * t.cny * t.cnz <= size_t(omc::kMaxCells)) break;
+        t.cshift += 1;
+    }
+    const int NE = omc::kNE;
+    std::vector<double> mh(NE, 0.0);
+    for (int i = 0; i < NE; ++i)
+        for (int m : c->present) mh[i] = std::max(mh[i], c->rho_max[m] * c->tabs[m].muTot[i]);
+    std::vector<double> r(omc::kMaxMaterials, 0.0);
+    for (size_t k = 0; k < c->present.size(); ++k)
+        for (int i = 0; i < NE; ++i) {
+            const double q = c->tabs[c->present[k]].muTot[i] / mh[i];
+            if (mh[i] > 0.0 && q > r[k]) r[k] = q;
+        }
+    if (!t.cellq && hipMalloc(&t.cellq, omc::kMaxCells * sizeof(uint32_t)) != hipSuccess) {
+        t.cellq = nullptr;
+        return fail(c, OMC_ENOMEM, "hipMalloc failed for the cell scales");
+    }
+    if (!t.cell_r && hipMalloc(&t.cell_r, omc::kMaxMaterials * sizeof(double)) != hipSuccess) {
+        t.cell_r = nullptr;
+        return fail(c, OMC_ENOMEM, "hipMalloc failed for the cell scales");
+    }
+    const std::vector<uint32_t> zero(omc::kMaxCells, 0u);
+    HIP_TRY(c, hipMemcpy(t.cellq, zero.data(), zero.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(t.cell_r, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (omc::launch_cell_scales(c->d_vox, c->nx, c->ny, c->nz, t.cshift, t.cnx, t.cny, t.cell_r,
+                                t.cellq, nullptr))
+        return fail(c, OMC_EDEVICE, "cell scale launch failed");
+    HIP_TRY(c, hipStreamSynchronize(nullptr));
+    return OMC_OK;
+}
+
 template <typename R>
 int device_tables(omc_ctx* c, DeviceTables<R>& t)
 {
@@ -329,6 +379,7 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
         (rc = upload(c, t.muhat, muhat)) || (rc = upload(c, t.msA, msA)) ||
         (rc = upload(c, t.Rabs, Rabs)))
         return rc;
+    if ((rc = cell_scales(c, t))) return rc;
     t.valid = true;
     return OMC_OK;
 }
@@ -851,6 +902,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     a.tab.msA = T.msA;
     a.tab.Rabs = T.Rabs;
     a.tab.n_mats = int(c->present.size());
+    a.cell = {T.cellq, T.cnx, T.cny, T.cnz, T.cshift};
     a.tab.L0 = R(g.L0);
     a.tab.DL = R(g.DL);
     a.tab.INV = R(g.INV);
@@ -887,7 +939,9 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     // requested work-groups per CU, 16 (130 KB, one work-group) from global
     const size_t lds_tabs = std::max(omc::photon_lds_bytes<R>(nm), omc::electron_lds_bytes<R>(nm));
     const bool gtab = P.table_mode == 2 || (P.table_mode == 0 && 2 * lds_tabs > size_t(lds_cu));
-    const size_t lds_ph = omc::photon_lds_bytes<R>(nm, gtab);
+    const bool cells = P.photon_mode == 1;
+    const size_t lds_ph =
+        omc::photon_lds_bytes<R>(nm, gtab, cells ? T.cnx * T.cny * T.cnz : 0);
     const size_t lds_el = omc::electron_lds_bytes<R>(nm, gtab);
     if (lds_ph > size_t(lds_max) || lds_el > size_t(lds_max))
         return fail(c, OMC_EUNSUP, "material tables exceed the LDS of a work-group; use "
@@ -921,7 +975,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
             a.qe_out = Q.q[ec];
             a.qp_out = Q.q[pc ^ 1];
             t.begin(1);
-            e = omc::Launch<R>::photon(a, tgrid, block, lds_ph, gtab, st);
+            e = omc::Launch<R>::photon(a, tgrid, block, lds_ph, gtab, cells, st);
             t.end();
         }
         a.qin = Q.q[ec];
@@ -997,7 +1051,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         const uint64_t shape[16] = {sizeof(R), N,      S,      uint64_t(K), uint64_t(block),
                                     uint64_t(tgrid),   lds_ph, lds_el,      uint64_t(P.timing),
                                     uint64_t(job.particle), need, uint64_t(P.electron_mode),
-                                    uint64_t(gtab), 0, 0, 0};
+                                    uint64_t(gtab), uint64_t(P.photon_mode), 0, 0};
         std::memcpy(key.data(), &a, sizeof a);
         std::memcpy(key.data() + sizeof a, shape, sizeof shape);
         if (!c->graph || key != c->graph_key) {
@@ -1360,6 +1414,7 @@ void omc_default_params(omc_params* p)
     p->straggler_lanes = 16;
     p->electron_mode = 0;
     p->table_mode = 0;
+    p->photon_mode = 0;
 }
 
 int check_phantom(const float* density, const uint8_t* material, size_t nvox, int n_mats,
@@ -1631,6 +1686,8 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
         return fail(c, OMC_EINVAL, "electron_mode must be 0 or 1");
     if (p->table_mode < 0 || p->table_mode > 2)
         return fail(c, OMC_EINVAL, "table_mode must be 0, 1 or 2");
+    if (p->photon_mode != 0 && p->photon_mode != 1)
+        return fail(c, OMC_EINVAL, "photon_mode must be 0 or 1");
     c->prm = *p;
     return OMC_OK;
 }
