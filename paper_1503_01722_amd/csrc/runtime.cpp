@@ -55,6 +55,7 @@ struct DeviceTables {
     uint32_t* cellq = nullptr;
     double* cell_r = nullptr;
     int cnx = 1, cny = 1, cnz = 1, cshift = 0;
+    bool cells_valid = false;  // built on the first photon_mode 1 run after the tables
     bool valid = false;
 };
 
@@ -379,7 +380,7 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
         (rc = upload(c, t.muhat, muhat)) || (rc = upload(c, t.msA, msA)) ||
         (rc = upload(c, t.Rabs, Rabs)))
         return rc;
-    if ((rc = cell_scales(c, t))) return rc;
+    t.cells_valid = false;
     t.valid = true;
     return OMC_OK;
 }
@@ -854,6 +855,10 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     int rc = device_tables(c, T);
     if (rc) return rc;
     const omc_params& P = c->prm;
+    if (P.photon_mode == 1 && !T.cells_valid) {
+        if ((rc = cell_scales(c, T))) return rc;
+        T.cells_valid = true;
+    }
     const uint64_t N = job.N;
     const uint64_t S = std::min<uint64_t>(
         P.chunk_histories > 0 ? uint64_t(P.chunk_histories) : (uint64_t(1) << 24), N);
