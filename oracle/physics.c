@@ -52,7 +52,7 @@ double orc_sigma_pe_atom(int Z, double E)
     return 1.25 * sigT * 4.0 * sqrt(2.0) * z5 * a4 * pow(MC2 / E, 3.5);
 }
 
-/* Pair production ("rough approximation", Sec. 2.1): Maximon's near-threshold
+/* Pair production (only roughly modelled in Sec. 2.1): Maximon's near-threshold
  * Born series in the nuclear field, with Z(Z+1) to include the electron field. */
 double orc_sigma_pair_atom(int Z, double E)
 {
