@@ -5,7 +5,7 @@
 //   photoelectric Born K-shell form of Heitler, times 5/4 for outer shells
 //                 (stand-in for the XCOM data the paper uses).
 //   pair          Maximon's near-threshold Born series with Z(Z+1) for the
-//                 electron field (the paper's "rough approximation").
+//                 electron field (the paper models pair production only roughly).
 // Electrons (Sec. 2.1: restricted stopping power, Moller, bremsstrahlung):
 //   collision     Bethe restricted to Moller transfers below Wcc, Fermi
 //                 asymptote of the density effect.
