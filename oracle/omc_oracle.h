@@ -28,7 +28,13 @@
  * closed forms against numerical quadrature, textbook limits and PDG/ESTAR
  * values; samplers by chi-square against analytic CDFs; Woodcock flights
  * against exp(-mu x); CSDA depth-dose against an independent range integral;
- * the energy ledger to 1e-9. The photoelectric and pair cross sections are
+ * the first real hard event of an electron against the survival
+ * exp(-integral sigma_hard) along its CSDA track; the mean direction cosine
+ * along a track against the product of the per-step exp(-s/lambda_1) and the
+ * first step's moments against the random hinge; momentum and energy balance
+ * of Compton and Moller events, the bremsstrahlung angle, isotropic
+ * annihilation; the energy ledger to 1e-9. Planted mistakes in a copy of the
+ * transport code fail these pins. The photoelectric and pair cross sections are
  * rough models (the paper uses XCOM data, absent here): they are pinned only
  * by their scaling laws and order of magnitude ("parity partially pinned").
  */
@@ -73,6 +79,7 @@ typedef struct {
     uint64_t el_steps, el_hard_cand, el_hard_fict, el_moller, el_brems, el_absorbed, el_escaped;
     uint64_t el_boundary, el_hinge_trunc, pos_annihil, push_ph, push_el, src_miss;
     double E_incident, E_deposited, E_escaped, E_pair_rest, E_annih_rest;
+    uint64_t watchdog; /* walks stopped by a bound that exact arithmetic never reaches */
 } orc_counters;
 
 typedef struct {
@@ -166,6 +173,25 @@ int orc_first_interaction(const orc_problem* p, uint32_t seed, uint32_t h0, uint
  * thread-safe. */
 int orc_trace(const orc_problem* p, uint32_t seed, uint32_t h, double* out, uint32_t cap,
               uint32_t* n_out);
+
+/* Step records of histories h0 .. h0+n-1, cap records each (history k at
+ * out + 12*cap*k, n_out[k] records). */
+int orc_trace_range(const orc_problem* p, uint32_t seed, uint32_t h0, uint32_t n, double* out,
+                    uint32_t cap, uint32_t* n_out);
+
+/* First accepted hard-event candidate of each source electron (voxel-limited
+ * steps): mass path before it (g/cm^2), energy at it, kind (1 Moller, 2
+ * bremsstrahlung, 0 none before absorption or escape). */
+int orc_first_hard(const orc_problem* p, uint32_t seed, uint32_t h0, uint32_t n, double* tau,
+                   double* T, int* kind);
+
+/* One interaction of the transport code per sample (see transport.c for the
+ * record layout of ORC_SAMPLE_WORDS doubles). */
+#define ORC_SAMPLE_WORDS 16
+enum { ORC_EV_COMPTON = 0, ORC_EV_MOLLER, ORC_EV_BREMS, ORC_EV_MS, ORC_EV_ANNIHILATION,
+       ORC_EV_PAIR, ORC_EV_SOURCE };
+int orc_sample_event(const orc_problem* p, int which, const double* args, uint32_t seed,
+                     uint32_t n, double* out, uint32_t* words);
 
 /* Full run of histories h0..h0+N-1. dose, dose2: nx*ny*nz, MeV/g per history
  * and sum over batches of the squared batch dose. Returns 0 or <0 on error. */

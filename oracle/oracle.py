@@ -8,6 +8,7 @@ dictionaries built by the seeded generators.
 The oracle follows the paper's Sec. 2.1 (physics), Sec. 2.2.2 (tally) and
 Sec. 3.1 (batch uncertainty); see ``omc_oracle.h`` for the list of pins.
 """
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -15,24 +16,28 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# OMC_ORACLE_LIB names another build of these sources (the tests that plant a
+# mistake in a copy of the oracle load that copy through it)
+_LIB_PATH = os.environ.get("OMC_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["rng.c", "physics.c", "transport.c"]
 NE = 512
 NA = 512
 MC2 = 0.51099895
 
 
-def build(force=True):
-    """Compile the oracle with gcc (-O2, OpenMP, no FMA contraction)."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
-    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
-    tmp = _LIB_PATH + ".tmp"
+def build(force=True, src_dir=None, lib_path=None):
+    """Compile the oracle with gcc (-O2, OpenMP, no FMA contraction); src_dir
+    and lib_path build another copy of the sources."""
+    lib_path = lib_path or _LIB_PATH
+    if not force and os.path.exists(lib_path):
+        return lib_path
+    srcs = [os.path.join(src_dir or _HERE, s) for s in _SOURCES]
+    tmp = lib_path + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 class Material(C.Structure):
@@ -54,10 +59,11 @@ COUNTER_FP = ["E_incident", "E_deposited", "E_escaped", "E_pair_rest", "E_annih_
 
 
 class Counters(C.Structure):
-    _fields_ = [(n, C.c_uint64) for n in COUNTER_INT] + [(n, C.c_double) for n in COUNTER_FP]
+    _fields_ = ([(n, C.c_uint64) for n in COUNTER_INT] + [(n, C.c_double) for n in COUNTER_FP]
+                + [("watchdog", C.c_uint64)])
 
     def as_dict(self):
-        return {n: getattr(self, n) for n in COUNTER_INT + COUNTER_FP}
+        return {n: getattr(self, n) for n in COUNTER_INT + COUNTER_FP + ["watchdog"]}
 
 
 class Problem(C.Structure):
@@ -80,6 +86,19 @@ class Problem(C.Structure):
 
 
 _lib = None
+
+
+@contextlib.contextmanager
+def library(path):
+    """Use another build of the oracle (a copy of the sources with a planted
+    mistake, for the tests that show a pin catches it) inside the block."""
+    global _lib, _LIB_PATH
+    saved = (_lib, _LIB_PATH)
+    _lib, _LIB_PATH = None, path
+    try:
+        yield lib()
+    finally:
+        _lib, _LIB_PATH = saved
 
 
 def lib():
@@ -141,6 +160,15 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(Problem), C.c_uint64, C.c_uint32, C.c_uint32, C.c_int,
                               dp, dp, C.POINTER(Counters)]
         L.orc_run.restype = C.c_int
+        L.orc_trace_range.argtypes = [C.POINTER(Problem), C.c_uint32, C.c_uint32, C.c_uint32, dp,
+                                      C.c_uint32, up]
+        L.orc_trace_range.restype = C.c_int
+        L.orc_first_hard.argtypes = [C.POINTER(Problem), C.c_uint32, C.c_uint32, C.c_uint32, dp,
+                                     dp, C.POINTER(C.c_int)]
+        L.orc_first_hard.restype = C.c_int
+        L.orc_sample_event.argtypes = [C.POINTER(Problem), C.c_int, dp, C.c_uint32, C.c_uint32,
+                                       dp, up]
+        L.orc_sample_event.restype = C.c_int
         _lib = L
     return _lib
 
@@ -345,3 +373,46 @@ def rotate(d, cost, sint, cphi, sphi):
 def fn(name):
     """Direct access to a closed-form function of the oracle library."""
     return getattr(lib(), name)
+
+
+def trace_range(phantom, source, n, seed=1, h0=0, params=None, cap=256):
+    """Electron step records of histories h0 .. h0+n-1 (see orc_trace_range):
+    a list of (records, 12) arrays."""
+    pr = _ProblemHolder(phantom, source, params)
+    out = np.zeros(12 * cap * n)
+    cnt = np.zeros(n, dtype=np.uint32)
+    if lib().orc_trace_range(C.byref(pr.struct), seed, h0, n, _dptr(out), cap, _uptr(cnt)) != 0:
+        raise ValueError("oracle rejected the problem")
+    out = out.reshape(n, cap, 12)
+    return [out[k, : cnt[k]] for k in range(n)]
+
+
+def first_hard(phantom, source, n, seed=1, h0=0, params=None):
+    """Mass path to, energy at and kind of the first accepted hard-event
+    candidate of each source electron (see orc_first_hard)."""
+    pr = _ProblemHolder(phantom, source, params)
+    tau, T = np.zeros(n), np.zeros(n)
+    kind = np.zeros(n, dtype=np.int32)
+    if lib().orc_first_hard(C.byref(pr.struct), seed, h0, n, _dptr(tau), _dptr(T),
+                            kind.ctypes.data_as(C.POINTER(C.c_int))) != 0:
+        raise ValueError("oracle rejected the problem")
+    return tau, T, kind
+
+
+SAMPLE_WORDS = 16
+EVENTS = {"compton": 0, "moller": 1, "brems": 2, "ms": 3, "annihilation": 4, "pair": 5,
+          "source": 6}
+
+
+def sample_event(which, args, n, phantom, source, seed=1, params=None):
+    """n samples of one interaction of the oracle's transport code (see
+    orc_sample_event): (records (n, 16), stream words used (n,))."""
+    pr = _ProblemHolder(phantom, source, params)
+    a = np.zeros(8)
+    a[: len(args)] = args
+    out = np.zeros(SAMPLE_WORDS * n)
+    words = np.zeros(n, dtype=np.uint32)
+    if lib().orc_sample_event(C.byref(pr.struct), EVENTS[which], _dptr(a), seed, n, _dptr(out),
+                              _uptr(words)) != 0:
+        raise ValueError("oracle rejected the problem")
+    return out.reshape(n, SAMPLE_WORDS), words

@@ -245,6 +245,16 @@ static double sample_ms(rng_t* r, double A)
     return 2.0 * A * u / (1.0 + A - u);
 }
 
+/* The hinge deflection of a step: polar angle from the screened-Rutherford
+ * form, azimuth uniform, applied to d; returns 1 - cos(theta). */
+static double ms_deflect(rng_t* r, double A, double d[3])
+{
+    const double omc = sample_ms(r, A);
+    const double phi = 2.0 * PI * rng_u(r);
+    orc_rotate(d, 1.0 - omc, sqrt(omc * (2.0 - omc)), cos(phi), sin(phi));
+    return omc;
+}
+
 /* --- secondaries ------------------------------------------------------------------ */
 static void emit_photon(const ctx_t* C, stack_t* st, tally_t* t, rng_t* parent, double E,
                         const double x[3], const int iv[3], const double d[3]);
@@ -354,7 +364,7 @@ static int woodcock_cells(const ctx_t* C, part_t* p, tally_t* t, size_t* vout, i
         t->c.ph_flights++;
         int c[3] = {p->iv[0] >> S, p->iv[1] >> S, p->iv[2] >> S};
         double mc = mh;
-        int inside = 0;
+        int inside = 0, left = 0;
         for (int n = 0; n < maxn; ++n) {
             const int q = C->cellq[c[0] + C->cn[0] * (c[1] + C->cn[1] * c[2])];
             mc = q == 255 ? mh : (mh * (double)q) / 255.0;
@@ -385,8 +395,14 @@ static int woodcock_cells(const ctx_t* C, part_t* p, tally_t* t, size_t* vout, i
             const int up = p->d[ax] > 0.0;
             p->x[ax] = (double)(c[ax] + up) * W[ax];
             c[ax] += up ? 1 : -1;
-            if (c[ax] < 0 || c[ax] >= C->cn[ax]) break;
+            if (c[ax] < 0 || c[ax] >= C->cn[ax]) {
+                left = 1;
+                break;
+            }
         }
+        /* a straight line crosses at most cn[0] + cn[1] + cn[2] cell faces;
+         * reaching the bound would be a rounding failure, not an escape */
+        if (!inside && !left) t->c.watchdog++;
         if (!inside || !locate(C, p->x, p->iv)) {
             t->c.E_escaped += p->E;
             t->c.ph_escaped++;
@@ -527,6 +543,15 @@ static void brems(const ctx_t* C, part_t* p, stack_t* st, tally_t* t)
     emit_photon(C, st, t, &p->rng, k, p->x, p->iv, dg);
 }
 
+/* Test hook (orc_first_hard): while active, voxel-limited electron steps add
+ * their mass path rho*s to tau, and the first accepted hard-event candidate
+ * records the energy there and its kind and ends the particle's transport.
+ * One history at a time (single-threaded use only). */
+static struct {
+    int active, done, kind;
+    double tau, T;
+} g_first;
+
 /* Candidate hard event at the end of an event-limited step: accepted with the
  * Woodcock ratio sigma(T_end)/sigma_hat(T_start) in mass units. */
 static void hard_event(const ctx_t* C, part_t* p, const orc_mat_tables* T, double shm,
@@ -540,7 +565,13 @@ static void hard_event(const ctx_t* C, part_t* p, const orc_mat_tables* T, doubl
     const double sB = lerp(T->sigB, i, f);
     const double sH = sM + sB;
     if (rng_u(&p->rng) * shm < sH) {
-        if (rng_u(&p->rng) * sH < sM) moller(C, p, st, t);
+        const int is_moller = rng_u(&p->rng) * sH < sM;
+        if (g_first.active && !g_first.done) {
+            g_first.done = 1;
+            g_first.kind = is_moller ? 1 : 2;
+            g_first.T = p->E;
+        }
+        if (is_moller) moller(C, p, st, t);
         else brems(C, p, st, t);
     } else {
         t->c.el_hard_fict++;
@@ -626,9 +657,7 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
                 const double Tmid = 0.5 * (T0 + Tplan);
                 const double xs = d * rho * orc_table_lookup(T->K1, Tmid);
                 const double A = orc_ms_screening(C->log2A, xs);
-                const double omc = sample_ms(&p->rng, A);
-                const double phi = 2.0 * PI * rng_u(&p->rng);
-                orc_rotate(p->d, 1.0 - omc, sqrt(omc * (2.0 - omc)), cos(phi), sin(phi));
+                ms_deflect(&p->rng, A, p->d);
                 const double rem = (1.0 - xi) * d;
                 int ax2;
                 const double dv2 = dist_to_face(C, p->iv, p->x, p->d, &ax2);
@@ -652,6 +681,7 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
             }
             t->c.el_steps++;
             p->E = Tend;
+            if (g_first.active) g_first.tau += rho * s;
         } else if (lim == LIM_VOX) {
             crossed = 1; /* zero-length step on a face: only the index moves */
         } else if (lim == LIM_ABS) {
@@ -677,6 +707,7 @@ static void transport_electron(const ctx_t* C, part_t* p, stack_t* st, tally_t* 
         }
         if (lim == LIM_EVENT) hard_event(C, p, T, shm, st, t);
         trace_step(C, p, 16 + lim);
+        if (g_first.active && g_first.done) return;
     }
 }
 
@@ -775,9 +806,7 @@ static void transport_electron_fixed(const ctx_t* C, part_t* p, stack_t* st, tal
                     const double Tplan = orc_range_inverse(T->R, RT - tau);
                     const double Tmid = 0.5 * (T0 + Tplan);
                     const double A = orc_ms_screening(C->log2A, tau * orc_table_lookup(T->K1, Tmid));
-                    const double omc = sample_ms(&p->rng, A);
-                    const double phi = 2.0 * PI * rng_u(&p->rng);
-                    orc_rotate(p->d, 1.0 - omc, sqrt(omc * (2.0 - omc)), cos(phi), sin(phi));
+                    ms_deflect(&p->rng, A, p->d);
                     out = march(C, p, t, T, RT, tau, lim == LIM_ABS, &done, &Tcur);
                 }
             }
@@ -1045,6 +1074,7 @@ static void counters_add(orc_counters* a, const orc_counters* b)
     a->E_escaped += b->E_escaped;
     a->E_pair_rest += b->E_pair_rest;
     a->E_annih_rest += b->E_annih_rest;
+    a->watchdog += b->watchdog;
 }
 
 int orc_run(const orc_problem* P, uint64_t N, uint32_t seed, uint32_t h0, int nthreads,
@@ -1221,4 +1251,177 @@ void orc_sample_ms(const double* log2A, double x, uint32_t seed, uint32_t n, dou
         rng_init(&r, seed, k, 0u, 0u);
         omc[k] = sample_ms(&r, A);
     }
+}
+
+/* Electron step records of histories h0 .. h0+n-1: history k gets up to cap
+ * records at out + 12*cap*k and n_out[k] is the number it made (see
+ * orc_trace). Single-threaded. */
+int orc_trace_range(const orc_problem* P, uint32_t seed, uint32_t h0, uint32_t n, double* out,
+                    uint32_t cap, uint32_t* n_out)
+{
+    ctx_t C;
+    if (ctx_init(&C, P, seed) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    tally_t t;
+    t.grid = (double*)calloc(C.nvox, sizeof(double));
+    memset(&t.c, 0, sizeof t.c);
+    stack_t st = {NULL, 0, 0};
+    for (uint32_t k = 0; k < n; ++k) {
+        g_trace = out + 12 * (size_t)cap * k;
+        g_trace_cap = cap;
+        g_trace_n = 0;
+        run_history(&C, h0 + k, &st, &t);
+        n_out[k] = g_trace_n < cap ? g_trace_n : cap;
+    }
+    g_trace = NULL;
+    free(st.a);
+    free(t.grid);
+    ctx_free(&C);
+    return 0;
+}
+
+/* For each source electron of histories h0 .. h0+n-1 (voxel-limited steps),
+ * the first accepted hard-event candidate: the mass path travelled before it
+ * (g/cm^2), the kinetic energy at it (the end of the step, before the event)
+ * and its kind (1 Moller, 2 bremsstrahlung; 0 when the electron was absorbed
+ * or escaped first, tau then being its whole mass path). Single-threaded. */
+int orc_first_hard(const orc_problem* P, uint32_t seed, uint32_t h0, uint32_t n, double* tau,
+                   double* T, int* kind)
+{
+    if (P->particle != 1 || P->electron_mode != 0 || P->kerma_mode) return -1;
+    ctx_t C;
+    if (ctx_init(&C, P, seed) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    tally_t t;
+    t.grid = (double*)calloc(C.nvox, sizeof(double));
+    memset(&t.c, 0, sizeof t.c);
+    stack_t st = {NULL, 0, 0};
+    for (uint32_t k = 0; k < n; ++k) {
+        part_t p;
+        tau[k] = -1.0;
+        T[k] = 0.0;
+        kind[k] = 0;
+        if (!source_particle(&C, h0 + k, &p)) continue;
+        memset(&g_first, 0, sizeof g_first);
+        g_first.active = 1;
+        st.n = 0;
+        transport_electron(&C, &p, &st, &t);
+        tau[k] = g_first.tau;
+        if (g_first.done) {
+            T[k] = g_first.T;
+            kind[k] = g_first.kind;
+        }
+    }
+    memset(&g_first, 0, sizeof g_first);
+    free(st.a);
+    free(t.grid);
+    ctx_free(&C);
+    return 0;
+}
+
+/* One interaction of the transport code above, sample k drawn from stream
+ * (seed, h = k, id 0) from block 0, on a particle with energy args[0] and
+ * unit direction args[1..3] in voxel (0, 0, 0) of the problem's phantom (the
+ * problem's Wcc, kc, E_abs and KERMA mode apply; E_abs = 0 keeps every
+ * product). Record of ORC_SAMPLE_WORDS doubles per sample:
+ *   [0] the particle's energy after the event, [1..3] its direction,
+ *   [4] products made, [5..8] and [9..12] product E, u, v, w,
+ *   [13], [14] product types (0 photon, 1 electron, 2 positron),
+ *   [15] the sampled variable: Compton E'/E, Moller W/T, bremsstrahlung k,
+ *        multiple scattering 1 - cos(theta) (args[4] = s/lambda_1 of the
+ *        step), pair T-/(E - 2 mc^2).
+ * which: ORC_EV_COMPTON, _MOLLER, _BREMS, _MS, _ANNIHILATION, _PAIR; for
+ * ORC_EV_SOURCE the source of the problem makes history k's particle:
+ * [0] its energy (0 for a miss), [1..3] direction, [5..7] entry point,
+ * [15] 1 if it entered the phantom. words[k]: the stream words used. */
+int orc_sample_event(const orc_problem* P, int which, const double* args, uint32_t seed,
+                     uint32_t n, double* out, uint32_t* words)
+{
+    ctx_t C;
+    if (which < ORC_EV_COMPTON || which > ORC_EV_SOURCE) return -1;
+    if (ctx_init(&C, P, seed) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    tally_t t;
+    t.grid = (double*)calloc(C.nvox, sizeof(double));
+    memset(&t.c, 0, sizeof t.c);
+    stack_t st = {NULL, 0, 0};
+    for (uint32_t k = 0; k < n; ++k) {
+        double* r = out + (size_t)ORC_SAMPLE_WORDS * k;
+        memset(r, 0, ORC_SAMPLE_WORDS * sizeof(double));
+        part_t p;
+        memset(&p, 0, sizeof p);
+        if (which == ORC_EV_SOURCE) {
+            const int hit = source_particle(&C, k, &p);
+            r[0] = hit ? p.E : 0.0;
+            for (int a = 0; a < 3; ++a) {
+                r[1 + a] = hit ? p.d[a] : 0.0;
+                r[5 + a] = hit ? p.x[a] : 0.0;
+            }
+            r[15] = hit;
+            /* the source draws block 0 only; transport continues at block 1 */
+            words[k] = 4u;
+            continue;
+        }
+        p.type = which == ORC_EV_MOLLER || which == ORC_EV_MS ? PT_ELECTRON
+               : which == ORC_EV_BREMS                       ? PT_ELECTRON
+               : which == ORC_EV_ANNIHILATION                ? PT_POSITRON
+                                                             : PT_PHOTON;
+        p.E = args[0];
+        for (int a = 0; a < 3; ++a) {
+            p.d[a] = args[1 + a];
+            p.x[a] = 0.5 * C.h[a];
+            p.iv[a] = 0;
+        }
+        p.nmfp = -1.0;
+        rng_init(&p.rng, seed, k, 0u, 0u);
+        st.n = 0;
+        const double E0 = p.E;
+        double v = 0.0;
+        switch (which) {
+        case ORC_EV_COMPTON:
+            compton(&C, &p, &st, &t);
+            v = p.E / E0;
+            break;
+        case ORC_EV_MOLLER:
+            moller(&C, &p, &st, &t);
+            v = st.n ? st.a[0].E / E0 : (E0 - p.E) / E0;
+            break;
+        case ORC_EV_BREMS:
+            brems(&C, &p, &st, &t);
+            v = E0 - p.E;
+            break;
+        case ORC_EV_MS:
+            v = ms_deflect(&p.rng, orc_ms_screening(C.log2A, args[4]), p.d);
+            break;
+        case ORC_EV_ANNIHILATION:
+            annihilate(&C, &st, &t, &p.rng, p.x, p.iv);
+            p.E = 0.0;
+            break;
+        case ORC_EV_PAIR:
+            pair(&C, &p, &st, &t);
+            v = st.n ? st.a[0].E / (E0 - 2.0 * MC2) : 0.0;
+            p.E = 0.0;
+            break;
+        }
+        r[0] = p.E;
+        for (int a = 0; a < 3; ++a) r[1 + a] = p.d[a];
+        r[4] = (double)st.n;
+        for (size_t j = 0; j < st.n && j < 2; ++j) {
+            r[5 + 4 * j] = st.a[j].E;
+            for (int a = 0; a < 3; ++a) r[6 + 4 * j + a] = st.a[j].d[a];
+            r[13 + j] = st.a[j].type;
+        }
+        r[15] = v;
+        words[k] = 4u * (p.rng.n - (p.rng.n > 0 ? 1u : 0u)) + (p.rng.n > 0 ? (uint32_t)p.rng.nw : 0u);
+    }
+    free(st.a);
+    free(t.grid);
+    ctx_free(&C);
+    return 0;
 }
