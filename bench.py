@@ -4,17 +4,22 @@
 A step is one full transport run (source, photon and electron generations in
 the launch shape given, FP64 tally fold) of the workload's histories, with
 phantom, tables and output buffers resident in HBM before the timed region.
-Default workload: 6 MV photons (64-bin synthetic spectrum), 10x10 cm^2 field at
-SSD 100 cm, 128^3 slab of 0.25 cm voxels (water / bone 1.85 / lung 0.26 /
-water), 1e7 histories per step, generations replayed from a captured graph.
-The batched workload (--workload beamlets_c4) steps through 512 beamlets on a
-256 x 256 x 160 CT-like phantom with per-beamlet sparse output left in HBM.
+Default workload: the largest single-GPU configuration, 15 MeV electrons from a
+point source at SSD 100 cm, 10x10 cm^2 field, on a 256^3 half-slab of 0.2 cm
+voxels (water, with bone 1.85 g/cm^3 filling x < 25.6 cm at depths 2-5 cm), 1e8
+histories per step, dose and dose^2 in FP64, generations replayed from a
+captured graph. --workload slab_6mv runs 6 MV photons (64-bin synthetic
+spectrum, 10x10 cm^2 at SSD 100 cm) on the 128^3 water/bone/lung/water slab of
+0.25 cm voxels, 1e7 histories per step. The batched workload (--workload
+beamlets_c4) steps through 512 beamlets on a 256 x 256 x 160 CT-like phantom
+with per-beamlet sparse output left in HBM.
 
 Prints one JSON line: histories/s, time to 1 % sigma at Dmax, the ALU roofline
 of the dominant kernel (algorithmic lane operations per launch over its
 HIP-event launch time, from an instrumented pass of the same steps right after
 the timed region: HIP events cannot time kernels inside a graph) and the CPU
-oracle timed on a bounded sample.
+oracle timed on a bounded sample, on every host core this process may use and
+on one core.
 """
 import argparse
 import json
@@ -64,6 +69,9 @@ WORKLOADS = {
     "beamlets_c4": "512 beamlets 0.5x0.5 cm2 of 6 MV (8 gantry angles x 8x8), 1e5-1e6 histories "
                    "each (2.84e8 in all), 256x256x160 CT-like phantom of 0.2 cm voxels (12 "
                    "seeded ellipsoids, 0.2-1.9 g/cm3), per-beamlet sparse FP32 dose in HBM",
+    "ceilings": "microbenchmarks of the ceilings: non-packed ALU lane-ops/s (FP32 FMA and "
+                "integer chains), HBM copy bytes/s, FP64 atomic adds/s at random addresses over "
+                "2^14..2^27 doubles and onto 1 or 64 contended addresses",
     "denoiser_128": "learned denoiser (4-level U-Net, 16/32/48/64 channels, BF16 matrix cores) "
                     "on 128^3 volumes: one training step (forward, backward, Adam) per step, "
                     "plus the forward (inference) time",
@@ -108,6 +116,18 @@ SHAPES = {
 }
 
 
+def host_cores():
+    """Host cores this process may run on: its CPU affinity, capped by
+    OMP_NUM_THREADS when the environment sets it (the share of the host a
+    job is given)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        cap = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        cap = 0
+    return max(1, min(n or 1, cap) if cap > 0 else (n or 1))
+
+
 def cpu_baseline(ph, src, target_s, threads, params=None):
     """The FP64 CPU oracle (test infrastructure) on a bounded sample of the same
     workload, as it stands."""
@@ -117,9 +137,9 @@ def cpu_baseline(ph, src, target_s, threads, params=None):
         # a CT volume: the oracle's own mapping gives the phantom it transports
         from oracle import ct
         ph = ct.phantom(ph["hu"], ph["voxel"], ph["materials"], ph["ct_map"])
-    # calibrate on two sizes so that the fixed set-up cost (tables, grids) is
-    # separated from the per-history cost
-    sizes, times = (20_000, 200_000), []
+    # calibrate on two sizes so that the fixed set-up cost (tables, per-thread
+    # batch grids) is separated from the per-history cost
+    sizes, times = (2_000 * threads, 12_000 * threads), []
     for n in sizes:
         t = time.perf_counter()
         oracle.run(ph, src, n, seed=7, threads=threads, params=params)
@@ -131,14 +151,15 @@ def cpu_baseline(ph, src, target_s, threads, params=None):
     oracle.run(ph, src, n_sample, seed=7, threads=threads, params=params)
     dt = time.perf_counter() - t
     return {"value": n_sample / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_sample} histories of the same workload (FP64 C oracle, OpenMP), "
-                      f"{dt:.1f} s"}
+            "sample": f"{n_sample} histories of the same workload (FP64 C oracle, OpenMP "
+                      f"threads {threads}), {dt:.1f} s including about {setup:.1f} s of fixed "
+                      f"set-up (tables, per-thread batch grids)"}
 
 
-def measured_traffic(kernel):
-    """HBM-side bytes per launch of `kernel` from the committed counter passes
-    (profiles/transport_counters.json), or None when the kernel sources have
-    changed since those counters were taken."""
+def measured_traffic(workload, kernel, shape):
+    """HBM-side bytes per launch of `kernel` on `workload` from the committed
+    counter passes (profiles/transport_counters.json), or None when the kernel
+    sources or the launch shape have changed since those counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "transport_counters.json")
     try:
@@ -148,12 +169,15 @@ def measured_traffic(kernel):
             h.update(open(os.path.join(ROOT, src), "rb").read())
         if h.hexdigest() != rec["source_sha256"]:
             return None
-        return rec["kernels"][kernel]["bytes_per_launch"]
-    except (OSError, KeyError, ValueError):
+        w = rec["workloads"][workload]
+        if any(w["launch"].get(k) != v for k, v in shape.items() if k in w["launch"]):
+            return None
+        return w["kernels"][kernel]["bytes_per_launch"]
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 
-def roofline_of(kt, units, fixed_steps=False):
+def roofline_of(kt, units, workload, shape, fixed_steps=False):
     """ALU roofline of the dominant transport kernel from per-kernel HIP-event
     times kt and the event counters units of the same steps."""
     dom = max(("photon", "electron"), key=lambda k: kt[k][0])
@@ -166,7 +190,8 @@ def roofline_of(kt, units, fixed_steps=False):
     achieved = ops / t_dom / 1e12
     return {"bound": "alu", "kernel": f"{dom}_kernel", "achieved": achieved,
             "peak": PEAK_ALU_TOPS, "unit": "Tops/s", "frac": achieved / PEAK_ALU_TOPS,
-            "traffic": measured_traffic(f"{dom}_kernel"), "traffic_unit": "bytes per launch",
+            "traffic": measured_traffic(workload, f"{dom}_kernel", shape),
+            "traffic_unit": "bytes per launch",
             "launches": launches, "avg_launch_ms": kt[dom][0] / launches,
             "ops_per_launch": ops / launches}
 
@@ -241,12 +266,50 @@ def bench_denoiser(args, omc, torch, np):
     print(json.dumps(res), flush=True)
 
 
+def measure_ceilings(footprints=(1 << 14, 1 << 20, 1 << 24, 1 << 27)):
+    """The MI355X ceilings the roofline fractions are taken against, measured
+    with the microbenchmarks of libomc_ceilings.so: the non-packed ALU rate
+    (FP32 FMA and integer chains, lane-ops/s), an HBM copy (bytes/s) and FP64
+    atomic adds at random addresses over several footprints and onto one
+    contended address (atomics/s)."""
+    import ctypes as C
+    L = C.CDLL(os.path.join(ROOT, "paper_1503_01722_amd", "_lib", "libomc_ceilings.so"))
+    ms, work = C.c_double(), C.c_double()
+    out = {}
+    for kind, name in ((0, "valu_fp32_fma"), (1, "valu_int")):
+        if L.omc_ceil_valu(kind, 8, 4096, 5, C.byref(ms), C.byref(work)) != 0:
+            raise RuntimeError("ALU microbenchmark failed")
+        out[name] = {"value": work.value / (ms.value / 1e3), "unit": "lane-ops/s",
+                     "ms": ms.value}
+    L.omc_ceil_stream.argtypes = [C.c_size_t, C.c_int, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
+    if L.omc_ceil_stream(1 << 31, 5, C.byref(ms), C.byref(work)) != 0:
+        raise RuntimeError("HBM microbenchmark failed")
+    out["hbm_copy"] = {"value": work.value / (ms.value / 1e3), "unit": "bytes/s",
+                       "bytes": work.value, "ms": ms.value}
+    L.omc_ceil_atomic.argtypes = [C.c_int, C.c_uint32, C.c_uint32, C.c_int, C.c_int,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    threads = 256 * 256 * 8
+    for fp in footprints:
+        if L.omc_ceil_atomic(0, fp, threads, 16, 5, C.byref(ms), C.byref(work)) != 0:
+            raise RuntimeError("atomic microbenchmark failed")
+        out[f"fp64_atomic_random_{fp}"] = {"value": work.value / (ms.value / 1e3),
+                                           "unit": "atomics/s", "footprint_doubles": fp,
+                                           "ms": ms.value}
+    for hot in (1, 64):
+        if L.omc_ceil_atomic(1, hot, threads, 16, 3, C.byref(ms), C.byref(work)) != 0:
+            raise RuntimeError("atomic microbenchmark failed")
+        out[f"fp64_atomic_hot_{hot}"] = {"value": work.value / (ms.value / 1e3),
+                                         "unit": "atomics/s", "addresses": hot, "ms": ms.value}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="slab_6mv", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="halfslab_e15", choices=sorted(WORKLOADS))
     ap.add_argument("--histories", type=int, default=0, help="override histories per step")
     ap.add_argument("--parity-fp64", action="store_true", help="time the FP64 parity build")
     ap.add_argument("--graph-depth", type=int, default=-1, help="override the launch shape")
@@ -297,6 +360,11 @@ def main():
         sys.exit(1)
     if args.workload == "denoiser_128":
         bench_denoiser(args, omc, torch, np)
+        return
+    if args.workload == "ceilings":
+        print(json.dumps({"metric": "ceilings", "config": {"workload": "ceilings",
+                                                           "description": WORKLOADS["ceilings"]},
+                          "ceilings": measure_ceilings()}), flush=True)
         return
     beamlets = args.workload == "beamlets_c4"
     if beamlets:
@@ -415,16 +483,20 @@ def main():
         out["events_per_history"] = {k: units[k] / (n * args.steps) for k in
                                      ("ph_flights", "ph_compton", "el_steps", "el_moller",
                                       "set_aside")}
-        out["roofline"] = roofline_of(kt, units, fixed_steps=args.electron_mode == 1)
+        launch = {k: params[k] for k in ("block_size", "blocks_per_cu", "chunk_histories",
+                                         "graph_depth")}
+        out["roofline"] = roofline_of(kt, units, args.workload, launch,
+                                      fixed_steps=args.electron_mode == 1)
     out["max_steps_per_particle"] = c["max_steps"]
     out["watchdog"] = c["watchdog"]
     if not args.no_cpu_baseline and not beamlets:
-        threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(ph, src, args.cpu_seconds, threads,
-                                           {"electron_mode": args.electron_mode})
+        # every core this process may use, then one core (the paper times its
+        # CPU build on 8 threads and on 1)
+        oparams = {"electron_mode": args.electron_mode}
+        out["cpu_baseline"] = cpu_baseline(ph, src, args.cpu_seconds, host_cores(), oparams)
+        out["cpu_baseline_1core"] = cpu_baseline(ph, src, args.cpu_seconds, 1, oparams)
     elif not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_beamlets(ph, job, args.cpu_seconds,
-                                                    min(16, os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline_beamlets(ph, job, args.cpu_seconds, host_cores())
     eng.close()
     print(json.dumps(out), flush=True)
 

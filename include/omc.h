@@ -189,12 +189,17 @@ typedef struct {
 
 void omc_default_params(omc_params* p);
 
-/* Create a context on the current HIP device. density: g/cm^3, finite and > 0;
- * material: ids < n_mats; mats: the material library, n_mats compositions
- * (1 <= n_mats <= OMC_MAX_MATERIALS; Sec. 2.1 supports 16, built from
- * user-defined compositions). Sizes: 1 <= nx,ny,nz <= 1024, voxel sizes > 0.
- * Builds the closed-form tables (Sec. 2.1) and uploads the phantom; the device
- * holds the tables of the materials present in the phantom only. */
+/* Create a context on the current HIP device for a voxelised phantom (Sec.
+ * 2.1: each voxel has a density and a material). density: g/cm^3, finite and
+ * > 0; material: ids < n_mats; mats: the material library, n_mats
+ * compositions (1 <= n_mats <= OMC_MAX_MATERIALS; Sec. 2.1 supports 16, built
+ * from user-defined compositions), copied; mats == NULL with n_mats 0 or 3
+ * selects the built-in library 0 water, 1 lung, 2 cortical bone (the
+ * materials of the paper's slab phantoms, Sec. 2.2 "Materials"). Sizes:
+ * 1 <= nx,ny,nz <= 1024, voxel sizes > 0. Builds the closed-form tables (Sec.
+ * 2.1) and uploads the phantom; the device holds the tables of the materials
+ * present in the phantom only. Errors: OMC_EINVAL for any invalid argument
+ * (*out is then NULL), OMC_EDEVICE without a device, OMC_ENOMEM. */
 int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
                const float* density, const uint8_t* material, const omc_material* mats,
                int n_mats);
@@ -239,6 +244,11 @@ int omc_set_source(omc_ctx* ctx, const omc_source* src);
 
 /* Set parameters (copied). Rebuilds the electron tables when Wcc or kc change. */
 int omc_set_params(omc_ctx* ctx, const omc_params* p);
+
+/* The phantom grid of a context: voxels per axis and voxel sizes in cm (the
+ * voxelised phantom of Sec. 2.1). Any output pointer may be NULL. */
+int omc_get_geometry(const omc_ctx* ctx, int* nx, int* ny, int* nz, double* dx, double* dy,
+                     double* dz);
 
 /* The context's current parameters (after omc_autotune, the tuned ones). */
 int omc_get_params(const omc_ctx* ctx, omc_params* out);
@@ -324,6 +334,32 @@ int omc_debug_philox(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_
  * the number written. Records of one particle are in step order. */
 int omc_debug_trace(omc_ctx* ctx, uint32_t seed, uint32_t h, double* out, uint32_t max_records,
                     uint32_t* n_records);
+
+/* Test entry: run one interaction of the transport code on the GPU, n times,
+ * for element-by-element comparison with a CPU implementation. Sample k draws
+ * from stream (seed, h = k, particle id 0) from block 0 (Sec. 2.2.3 gives each
+ * work-item its own random stream) and acts on a particle of energy args[0]
+ * (MeV) and unit direction args[1..3] in voxel (0, 0, 0) of the context's
+ * phantom, with the context's Wcc and kc and its precision (parity_fp64);
+ * every product is kept (absorption energies and KERMA mode do not apply).
+ * which (Sec. 2.1 physics):
+ *   0 Compton scattering (Klein-Nishina), 1 Moller event, 2 bremsstrahlung
+ *   event, 3 multiple-scattering deflection of a step with args[4] =
+ *   s / lambda_1, 4 positron annihilation at rest, 5 pair production,
+ *   6 the context's source (Sec. 2.2 "Materials"): history k's entering
+ *   particle (args unused; omc_set_source first, else OMC_ESTATE).
+ * out: n records of 16 doubles (host memory, caller-owned): [0] the
+ * particle's energy after the event, [1..3] its direction, [4] products made,
+ * [5..8] and [9..12] the first two products' energy and direction, [13] and
+ * [14] their types (0 photon, 1 electron, 2 positron), [15] the sampled
+ * variable: Compton E'/E, Moller W/T, bremsstrahlung k (MeV), 1 - cos(theta),
+ * pair T-/(E - 2 mc^2). For the source: [0] energy (0 when the ray misses the
+ * phantom), [1..3] direction, [5..7] entry point (cm), [15] 1 if it entered.
+ * words: n stream words used (host memory). 1 <= n <= 2^22; E in (0, 20] MeV;
+ * pair needs E > 2 mc^2; else OMC_EINVAL. Synchronous; allocates and frees
+ * its own device scratch. */
+int omc_debug_sample(omc_ctx* ctx, int which, const double* args, uint32_t seed, uint32_t n,
+                     double* out, uint32_t* words);
 
 /* Host-only (no device needed): the engine's own table builder. out receives
  * OMC_TABLE_ROWS x OMC_NE doubles in the row order muC, muPE, muPair, muTot,

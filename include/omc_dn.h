@@ -86,7 +86,9 @@ int omc_dn_gradient(omc_dn* dn, const float* d_dose, const float* d_sigma, const
  * cannot explain). If err > max_err, n_fallback more histories (following
  * history ids) are transported and d_out is the plain Monte Carlo dose of all
  * n_low + n_fallback histories. d_out: device float32 volume. *err receives
- * the estimate, *fell_back 0 or 1. */
+ * the estimate, *fell_back 0 or 1. A phantom whose nx, ny, nz differ from the
+ * network's, or d_rho / d_out that are not device allocations of the network's
+ * device holding one float per voxel, give OMC_EINVAL before any launch. */
 int omc_dn_denoise(omc_dn* dn, omc_ctx* ctx, uint64_t n_low, uint32_t seed, uint32_t h0,
                    const float* d_rho, double max_err, uint64_t n_fallback, float* d_out,
                    double* err, int* fell_back, void* hip_stream);

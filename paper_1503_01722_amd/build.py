@@ -9,6 +9,8 @@ Translation units:
   phantom_kernels.hip  voxel records and the CT mapping, without FMA contraction
   dn_kernels.hip   denoiser kernels (BF16 matrix-core convolutions, loss, Adam)
   dn_runtime.cpp   denoiser network, training and the C ABI of include/omc_dn.h
+and, apart, ``_lib/libomc_ceilings.so`` from ceilings.hip: the microbenchmarks
+of the ALU, HBM and FP64-atomic ceilings the measurement reports against.
 """
 import os
 import shutil
@@ -52,11 +54,23 @@ def _compile(src, extra):
     return obj
 
 
+# the ceiling microbenchmarks: a library of their own (measurement only)
+CEIL_UNITS = {"ceilings.hip": []}
+CEIL_LIB = os.path.join(LIBDIR, "libomc_ceilings.so")
+
+
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     os.makedirs(LIBDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+    with ThreadPoolExecutor(max_workers=len(UNITS) + len(CEIL_UNITS)) as ex:
         objs = list(ex.map(lambda kv: _compile(*kv), UNITS.items()))
+        ceil_objs = list(ex.map(lambda kv: _compile(*kv), CEIL_UNITS.items()))
+    tmp = CEIL_LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + ceil_objs
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd="/tmp")
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n" + r.stderr)
+    os.replace(tmp, CEIL_LIB)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True, cwd="/tmp")

@@ -500,6 +500,25 @@ int omc_dn_train_step(omc_dn* d, const float* dose, const float* sigma, const fl
     return read_loss(d, s, loss);
 }
 
+namespace {
+// True when [p, p + bytes) lies inside one HIP allocation of the network's
+// device, so that a caller's buffer is checked before any kernel touches it.
+bool on_device(const omc_dn* d, const void* p, size_t bytes)
+{
+    hipPointerAttribute_t at{};
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    const bool dev = hipPointerGetAttributes(&at, p) == hipSuccess &&
+                     at.type == hipMemoryTypeDevice && at.device == d->device;
+    const bool range =
+        dev && hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess &&
+        reinterpret_cast<uintptr_t>(p) >= reinterpret_cast<uintptr_t>(base) &&
+        reinterpret_cast<uintptr_t>(p) + bytes <= reinterpret_cast<uintptr_t>(base) + size;
+    (void)hipGetLastError();
+    return dev && range && reinterpret_cast<uintptr_t>(p) % alignof(float) == 0;
+}
+}  // namespace
+
 int omc_dn_denoise(omc_dn* d, omc_ctx* ctx, uint64_t n_low, uint32_t seed, uint32_t h0,
                    const float* d_rho, double max_err, uint64_t n_fallback, float* out,
                    double* err, int* fell_back, void* hip_stream)
@@ -510,6 +529,21 @@ int omc_dn_denoise(omc_dn* d, omc_ctx* ctx, uint64_t n_low, uint32_t seed, uint3
     if (hipSetDevice(d->device) != hipSuccess) return dn_fail(d, OMC_EDEVICE, "hipSetDevice failed");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const size_t n = d->lv[0].n;
+    // the engine writes its dose grids into buffers sized for the network's
+    // volume: the phantom must have exactly the network's dimensions
+    int nx = 0, ny = 0, nz = 0;
+    if (omc_get_geometry(ctx, &nx, &ny, &nz, nullptr, nullptr, nullptr) != OMC_OK)
+        return dn_fail(d, OMC_EINVAL, "invalid context");
+    if (nx != d->lv[0].d.nx || ny != d->lv[0].d.ny || nz != d->lv[0].d.nz)
+        return dn_fail(d, OMC_EINVAL, "the context's phantom (" + std::to_string(nx) + " x " +
+                                          std::to_string(ny) + " x " + std::to_string(nz) +
+                                          ") does not have the network's dimensions (" +
+                                          std::to_string(d->lv[0].d.nx) + " x " +
+                                          std::to_string(d->lv[0].d.ny) + " x " +
+                                          std::to_string(d->lv[0].d.nz) + ")");
+    if (!on_device(d, d_rho, n * sizeof(float)) || !on_device(d, out, n * sizeof(float)))
+        return dn_fail(d, OMC_EINVAL, "d_rho and out must be allocations of the network's "
+                                      "device holding one float per voxel");
     if (!d->d64 && !(dalloc(d, d->d64, 4 * n) && dalloc(d, d->f32, 2 * n)))
         return dn_fail(d, OMC_ENOMEM, "device allocation failed");
     omc_params prm;

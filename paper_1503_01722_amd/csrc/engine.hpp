@@ -62,6 +62,7 @@ enum Energy : int { EN_INCIDENT = 0, EN_DEPOSITED, EN_ESCAPED, kNumEnergies };
 enum PType : int { PT_PHOTON = 0, PT_ELECTRON = 1, PT_POSITRON = 2 };
 
 constexpr uint32_t kResBlockSlots = 128;  // output slots a wave reserves per atomic
+constexpr uint32_t kHoleTag = 0xFFFFFFFFu;  // queue slot reserved but never filled
 constexpr int kTabNE = 512;
 constexpr int kTabNA = 512;
 constexpr int kRangeCells = 1024;  // range-inverse index cells per material
@@ -231,6 +232,24 @@ inline size_t electron_lds_bytes(int n_mats, bool gtab = false)
            sizeof(R) * kTabNA + sizeof(R) * ((size_t(n_mats) + 7) & ~size_t(7));
 }
 
+// Test-only sampler (omc_debug_sample): one interaction per work-item.
+enum SampleKind : int {
+    SMP_COMPTON = 0,
+    SMP_MOLLER,
+    SMP_BREMS,
+    SMP_MS,
+    SMP_ANNIHILATION,
+    SMP_PAIR,
+    SMP_SOURCE
+};
+constexpr int kSampleWords = 16;
+struct SampleArgs {
+    int which;
+    uint32_t seed, n;
+    double E, u, v, w;  // the particle before the event
+    double x;           // multiple scattering: s / lambda_1 of the step
+};
+
 // Host-side launchers (one instantiation per precision).
 template <typename R>
 struct Launch {
@@ -242,6 +261,8 @@ struct Launch {
     // fixed: steps across voxels (electron_mode 1), a kernel of its own
     static int electron(const KernelArgs<R>& a, int grid, int block, size_t lds, bool fixed,
                         bool gtab, void* stream);
+    static int sample(const KernelArgs<R>& a, const SampleArgs& sa, double* out,
+                      uint32_t* words, void* stream);
 };
 
 int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,

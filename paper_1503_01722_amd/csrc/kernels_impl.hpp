@@ -77,4 +77,13 @@ int Launch<R>::electron(const KernelArgs<R>& a, int grid, int block, size_t lds,
     return detail::launch_status();
 }
 
+template <typename R>
+int Launch<R>::sample(const KernelArgs<R>& a, const SampleArgs& sa, double* out, uint32_t* words,
+                      void* stream)
+{
+    hipLaunchKernelGGL(sample_kernel<R>, dim3((sa.n + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, a, sa, out, words);
+    return detail::launch_status();
+}
+
 }  // namespace omc

@@ -722,7 +722,8 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 // Lay the job's beams out in device memory (one upload, asynchronous on s; the
 // host copy stays alive in the context until the run has synchronised).
 template <typename R>
-int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& v)
+int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& v,
+                 char* fixed = nullptr, size_t fixed_cap = 0)
 {
     const size_t nb = job.beams.size();
     std::vector<omc::BeamSrc<R>> bs(nb);
@@ -795,7 +796,16 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
     const size_t o_edges = o_cdf + align256(std::max<size_t>(cdf.size(), 1) * sizeof(double));
     const size_t o_psf = o_edges + align256(std::max<size_t>(edges.size(), 1) * sizeof(R));
     const size_t total = o_psf + align256(std::max<size_t>(recs.size(), 1) * sizeof(float));
-    if (c->src_cap < total) {
+    if (fixed) {
+        // a run that may not allocate: the description goes into the fixed
+        // buffer, and a resident phase space must be on the device already
+        if (total > fixed_cap)
+            return fail(c, OMC_EINVAL, "the source description exceeds the fixed scratch");
+        if (resident && (c->psf_dirty || !c->d_psf))
+            return fail(c, OMC_ESTATE, "the phase-space records are not on the device yet: "
+                                       "run omc_run or omc_run_device once after "
+                                       "omc_set_source");
+    } else if (c->src_cap < total) {
         dfree(c->d_src);
         c->src_cap = 0;
         const size_t want = std::max<size_t>(total, 64 * 1024);
@@ -805,7 +815,7 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
         }
         c->src_cap = want;
     }
-    if (resident && (c->psf_dirty || !c->d_psf)) {
+    if (!fixed && resident && (c->psf_dirty || !c->d_psf)) {
         if (c->psf_cap < c->psf.size()) {
             dfree(c->d_psf);
             c->psf_cap = 0;
@@ -820,11 +830,12 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
                                   hipMemcpyHostToDevice, s));
         c->psf_dirty = false;
     }
-    // record pointers: the resident copy, or this job's records in d_src
+    char* const dst = fixed ? fixed : c->d_src;
+    // record pointers: the resident copy, or this job's records in the description
     for (size_t b = 0; b < nb; ++b)
         if (bs[b].n_psf > 0 && !job.beams[b].psf_dev)
             bs[b].psf = rec_at[b] < 0 ? c->d_psf
-                                      : reinterpret_cast<const float*>(c->d_src + o_psf) + rec_at[b];
+                                      : reinterpret_cast<const float*>(dst + o_psf) + rec_at[b];
     c->src_stage.assign(total, 0);
     char* h = c->src_stage.data();
     std::memcpy(h + o_beams, bs.data(), nb * sizeof(omc::BeamSrc<R>));
@@ -832,11 +843,11 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
     if (!cdf.empty()) std::memcpy(h + o_cdf, cdf.data(), cdf.size() * sizeof(double));
     if (!edges.empty()) std::memcpy(h + o_edges, edges.data(), edges.size() * sizeof(R));
     if (!recs.empty()) std::memcpy(h + o_psf, recs.data(), recs.size() * sizeof(float));
-    HIP_TRY(c, hipMemcpyAsync(c->d_src, h, total, hipMemcpyHostToDevice, s));
-    v.beams = reinterpret_cast<const omc::BeamSrc<R>*>(c->d_src + o_beams);
-    v.first = reinterpret_cast<const uint64_t*>(c->d_src + o_first);
-    v.cdf = reinterpret_cast<const double*>(c->d_src + o_cdf);
-    v.edges = reinterpret_cast<const R*>(c->d_src + o_edges);
+    HIP_TRY(c, hipMemcpyAsync(dst, h, total, hipMemcpyHostToDevice, s));
+    v.beams = reinterpret_cast<const omc::BeamSrc<R>*>(dst + o_beams);
+    v.first = reinterpret_cast<const uint64_t*>(dst + o_first);
+    v.cdf = reinterpret_cast<const double*>(dst + o_cdf);
+    v.edges = reinterpret_cast<const R*>(dst + o_edges);
     v.n_beams = int(nb);
     v.particle = job.particle;
     v.cell_mode = job.cell_mode;
@@ -846,49 +857,67 @@ int pack_sources(omc_ctx* c, const Job& job, hipStream_t s, omc::SourceView<R>& 
 // ----------------------------------------------------------------- transport
 // Transport every history of the job into the cell grids; the statistics stay
 // on the device (finish_stats reads them). L.iterations counts generations.
-template <typename R>
-int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTimer& tm,
-              omc_counters& L)
+// Device memory of a run besides the phantom and the tables: the context's
+// own buffers (queues and tally grids allocated on demand), or regions of the
+// library's fixed scratch array for a run that may not allocate.
+struct RunMem {
+    uint32_t* ctrl;                 // [64]: queue {count, head} x 4, overflow, ...
+    unsigned long long* counters;   // [rows][kNumCounters]
+    double* energies;               // [rows][kNumEnergies]
+    uint32_t rows;
+    omc::RunDesc* run;
+    double* grid;                   // tally cells (set by transport for the context's own)
+    bool fixed = false;             // the regions below are given: allocate nothing
+    char* src = nullptr;            // source description
+    size_t src_cap = 0;
+    char* queues = nullptr;         // four queues
+    size_t queue_bytes = 0;
+    size_t grid_cap = 0;            // doubles the fixed grid region holds
+};
+
+RunMem ctx_mem(omc_ctx* c)
 {
-    DeviceTables<R>& T = tables_of(c, R());
-    DeviceQueues<R>& Q = queues_of(c, R());
-    int rc = device_tables(c, T);
-    if (rc) return rc;
+    return RunMem{c->d_ctrl, c->d_counters, c->d_energies, omc::kStatsRows, c->d_run, c->d_grid};
+}
+
+// Four queues of cap records each carved from a fixed region (the layout of
+// ensure_queues); the counts and heads live in ctrl.
+template <typename R>
+void carve_queues(char* base, uint32_t cap, uint32_t* ctrl, omc::QueueView<R> q[4])
+{
+    char* p = base;
+    auto take = [&p](size_t n) {
+        char* r = p;
+        p += (n + 255) & ~size_t(255);
+        return r;
+    };
+    for (int k = 0; k < 4; ++k) {
+        q[k].x = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].y = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].z = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].u = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].v = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].w = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].E = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].vox = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q[k].hist = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q[k].qlo = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q[k].qhi = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q[k].tag = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q[k].aux_pos = reinterpret_cast<uint32_t*>(take(cap * sizeof(uint32_t)));
+        q[k].aux_f = reinterpret_cast<R*>(take(cap * sizeof(R)));
+        q[k].cap = cap;
+        q[k].count = ctrl + 2 * k;
+        q[k].head = ctrl + 2 * k + 1;
+    }
+}
+
+// Kernel arguments that depend on the context only: phantom, tables, cells
+// and transport parameters (the rest zero).
+template <typename R>
+omc::KernelArgs<R> phantom_args(const omc_ctx* c, const DeviceTables<R>& T)
+{
     const omc_params& P = c->prm;
-    if (P.photon_mode == 1 && !T.cells_valid) {
-        if ((rc = cell_scales(c, T))) return rc;
-        T.cells_valid = true;
-    }
-    const uint64_t N = job.N;
-    const uint64_t S = std::min<uint64_t>(
-        P.chunk_histories > 0 ? uint64_t(P.chunk_histories) : (uint64_t(1) << 24), N);
-    // capacity: secondaries per source history, plus the holes left by the
-    // per-wave slot reservations of the two kernels that append to a queue
-    const uint64_t waves = uint64_t(c->cu_count) * P.blocks_per_cu * (P.block_size / 64);
-    const uint64_t qcap = std::min<uint64_t>(
-        uint64_t(P.queue_factor) * S + 2 * waves * omc::kResBlockSlots + 4096, 0x7fffffffull);
-    if ((rc = ensure_queues(c, Q, uint32_t(std::max<uint64_t>(qcap, S)), uint32_t(qcap)))) return rc;
-
-    const size_t need = size_t(job.cells) * c->nvox;
-    if (c->grid_cells < size_t(job.cells)) {
-        drop_graph(c);
-        dfree(c->d_grid);
-        c->grid_cells = 0;
-        if (hipMalloc(&c->d_grid, need * sizeof(double)) != hipSuccess) {
-            c->d_grid = nullptr;
-            return fail(c, OMC_ENOMEM, "hipMalloc failed for the tally grids");
-        }
-        c->grid_cells = size_t(job.cells);
-    }
-    // launch checks read the runtime's last error: start from a clean state
-    (void)hipGetLastError();
-    omc::SourceView<R> sv{};
-    if ((rc = pack_sources(c, job, s, sv))) return rc;
-    c->h_run->seed = seed;
-    c->h_run->n_batches = job.cell_mode ? 0u : uint32_t(job.cells);
-    c->h_run->n_total = N;
-    HIP_TRY(c, hipMemcpyAsync(c->d_run, c->h_run, sizeof(omc::RunDesc), hipMemcpyHostToDevice, s));
-
     omc::KernelArgs<R> a;
     std::memset(&a, 0, sizeof a);
     a.ph = {c->d_rho, c->d_mat, c->nx, c->ny, c->nz, R(c->dx), R(c->dy), R(c->dz),
@@ -921,18 +950,96 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     const double skin = 1e-3 * std::fmin(c->dx, std::fmin(c->dy, c->dz));
     a.prm = {R(P.Eabs_e), R(P.Eabs_g), R(P.Wcc), R(P.kc), R(P.dmax_s), R(1.0 - P.f_E), R(skin),
              P.kerma_mode, P.csda_mode};
-    a.tally = {c->d_grid, c->nvox};
-    a.stats = {c->d_counters, c->d_energies, omc::kStatsRows, c->d_ctrl + 8, c->d_ctrl + 9,
-               c->d_ctrl + 10};
+    return a;
+}
+
+template <typename R>
+int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTimer& tm,
+              omc_counters& L, RunMem& M)
+{
+    DeviceTables<R>& T = tables_of(c, R());
+    int rc;
+    const omc_params& P = c->prm;
+    if (M.fixed) {
+        // nothing may be allocated: the tables (and cell scales) must exist
+        if (!T.valid || (P.photon_mode == 1 && !T.cells_valid))
+            return fail(c, OMC_ESTATE, "the physics tables of this precision are not on the "
+                                       "device yet: run omc_run or omc_run_device once first");
+    } else {
+        if ((rc = device_tables(c, T))) return rc;
+        if (P.photon_mode == 1 && !T.cells_valid) {
+            if ((rc = cell_scales(c, T))) return rc;
+            T.cells_valid = true;
+        }
+    }
+    const uint64_t N = job.N;
+    const size_t need = size_t(job.cells) * c->nvox;
+    omc::QueueView<R> Qv[4];
+    uint64_t S;
+    int block, tgrid;
+    if (M.fixed) {
+        // one wave per CU keeps the holes of the per-wave slot reservations
+        // small; the chunk is what the queue region then holds
+        block = 64;
+        tgrid = c->cu_count;
+        const size_t per = 8 * sizeof(R) + 6 * sizeof(uint32_t);
+        // a multiple of 64 records: every array of a queue 256-byte aligned
+        const uint64_t cap = ((M.queue_bytes / 4) / per) & ~uint64_t(63);
+        const uint64_t slack = 2 * uint64_t(tgrid) * omc::kResBlockSlots + 4096;
+        const uint64_t qf = uint64_t(std::max(P.queue_factor, 1));
+        if (cap <= slack || (cap - slack) / qf < 1 || cap > 0x7fffffc0ull)
+            return fail(c, OMC_EUNSUP, "the fixed scratch holds no queue for this device");
+        S = std::min<uint64_t>((cap - slack) / qf, N);
+        if (P.chunk_histories > 0) S = std::min<uint64_t>(S, uint64_t(P.chunk_histories));
+        if (need > M.grid_cap)
+            return fail(c, OMC_EINVAL, "the tally grids (n_batches x voxels) exceed the fixed "
+                                       "scratch; use fewer batches or omc_run_device");
+        carve_queues<R>(M.queues, uint32_t(cap), M.ctrl, Qv);
+    } else {
+        DeviceQueues<R>& Q = queues_of(c, R());
+        S = std::min<uint64_t>(
+            P.chunk_histories > 0 ? uint64_t(P.chunk_histories) : (uint64_t(1) << 24), N);
+        block = P.block_size;
+        tgrid = c->cu_count * P.blocks_per_cu;
+        // capacity: secondaries per source history, plus the holes left by the
+        // per-wave slot reservations of the two kernels that append to a queue
+        const uint64_t waves = uint64_t(tgrid) * (block / 64);
+        const uint64_t qcap = std::min<uint64_t>(
+            uint64_t(P.queue_factor) * S + 2 * waves * omc::kResBlockSlots + 4096, 0x7fffffffull);
+        if ((rc = ensure_queues(c, Q, uint32_t(std::max<uint64_t>(qcap, S)), uint32_t(qcap))))
+            return rc;
+        for (int k = 0; k < 4; ++k) Qv[k] = Q.q[k];
+        if (c->grid_cells < size_t(job.cells)) {
+            drop_graph(c);
+            dfree(c->d_grid);
+            c->grid_cells = 0;
+            if (hipMalloc(&c->d_grid, need * sizeof(double)) != hipSuccess) {
+                c->d_grid = nullptr;
+                return fail(c, OMC_ENOMEM, "hipMalloc failed for the tally grids");
+            }
+            c->grid_cells = size_t(job.cells);
+        }
+        M.grid = c->d_grid;
+    }
+    // launch checks read the runtime's last error: start from a clean state
+    (void)hipGetLastError();
+    omc::SourceView<R> sv{};
+    if ((rc = pack_sources(c, job, s, sv, M.fixed ? M.src : nullptr, M.src_cap))) return rc;
+    c->h_run->seed = seed;
+    c->h_run->n_batches = job.cell_mode ? 0u : uint32_t(job.cells);
+    c->h_run->n_total = N;
+    HIP_TRY(c, hipMemcpyAsync(M.run, c->h_run, sizeof(omc::RunDesc), hipMemcpyHostToDevice, s));
+
+    omc::KernelArgs<R> a = phantom_args(c, T);
+    a.tally = {M.grid, c->nvox};
+    a.stats = {M.counters, M.energies, M.rows, M.ctrl + 8, M.ctrl + 9, M.ctrl + 10};
     a.src = sv;
     a.trace = c->trace;
-    a.run = c->d_run;
+    a.run = M.run;
     a.chunk = 64;
     a.min_grid = c->cu_count;
     a.spill_lanes = P.straggler_lanes;
 
-    const int block = P.block_size;
-    const int tgrid = c->cu_count * P.blocks_per_cu;
     const int nm = int(c->present.size());
     int lds_max = 0, lds_cu = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
@@ -957,44 +1064,44 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     c->timing.tables_global = gtab ? 1 : 0;
 
     auto zero_all = [&](hipStream_t st) {
-        return omc::launch_zero(c->d_grid, need, st) ||
-               omc::launch_zero(c->d_counters, size_t(omc::kStatsRows) * omc::kNumCounters, st) ||
-               omc::launch_zero(c->d_energies, size_t(omc::kStatsRows) * omc::kNumEnergies, st) ||
-               omc::launch_zero(c->d_ctrl, 8, st);
+        return omc::launch_zero(M.grid, need, st) ||
+               omc::launch_zero(M.counters, size_t(M.rows) * omc::kNumCounters, st) ||
+               omc::launch_zero(M.energies, size_t(M.rows) * omc::kNumEnergies, st) ||
+               omc::launch_zero(M.ctrl, 8, st);
     };
     auto source = [&](uint64_t begin, uint32_t cnt, int pc, int ec, hipStream_t st,
                       EventTimer& t) {
-        a.qp_out = Q.q[pc];
-        a.qe_out = Q.q[ec];
+        a.qp_out = Qv[pc];
+        a.qe_out = Qv[ec];
         a.src_begin = begin;
         a.src_count = cnt;
         t.begin(0);
         const int e = omc::Launch<R>::source(a, int((cnt + 255) / 256), 256, st);
         t.end();
-        return e || omc::launch_queue_commit(c->d_ctrl, job.particle == 0 ? pc : ec, cnt, st);
+        return e || omc::launch_queue_commit(M.ctrl, job.particle == 0 ? pc : ec, cnt, st);
     };
     auto generation = [&](int pc, int ec, bool photons, hipStream_t st, EventTimer& t) {
         int e = 0;
         if (photons) {
-            a.qin = Q.q[pc];
-            a.qe_out = Q.q[ec];
-            a.qp_out = Q.q[pc ^ 1];
+            a.qin = Qv[pc];
+            a.qe_out = Qv[ec];
+            a.qp_out = Qv[pc ^ 1];
             t.begin(1);
             e = omc::Launch<R>::photon(a, tgrid, block, lds_ph, gtab, cells, st);
             t.end();
         }
-        a.qin = Q.q[ec];
-        a.qe_out = Q.q[ec ^ 1];
-        a.qp_out = Q.q[pc ^ 1];
+        a.qin = Qv[ec];
+        a.qe_out = Qv[ec ^ 1];
+        a.qp_out = Qv[pc ^ 1];
         t.begin(2);
         e = e || omc::Launch<R>::electron(a, tgrid, block, lds_el, P.electron_mode == 1, gtab,
                                           st);
         t.end();
-        return e || omc::launch_queue_reset(c->d_ctrl, (1 << pc) | (1 << ec), st);
+        return e || omc::launch_queue_reset(M.ctrl, (1 << pc) | (1 << ec), st);
     };
     uint32_t iters = 0;
     auto readback = [&](int pc, int ec, uint32_t& n_ph, uint32_t& n_el) -> int {
-        HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 16 * sizeof(uint32_t),
+        HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, M.ctrl, 16 * sizeof(uint32_t),
                                   hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         if (c->h_ctrl[8])
@@ -1020,7 +1127,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     };
 
     int pc = 0, ec = 2;  // current photon / electron queues
-    if (P.graph_depth > 0 && P.timing) {
+    if (!M.fixed && P.graph_depth > 0 && P.timing) {
         // HIP events do not time kernels inside a graph: the timed variant
         // launches the same fixed-depth sequence eagerly, one event pair per
         // launch (same kernels, same grids, same carry-over)
@@ -1039,7 +1146,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         uint32_t n_ph = 0, n_el = 0;
         if ((rc = readback(pc, ec, n_ph, n_el))) return rc;
         if ((rc = drain(pc, ec, n_ph, n_el))) return rc;
-    } else if (P.graph_depth <= 0) {
+    } else if (M.fixed || P.graph_depth <= 0) {
         if (zero_all(s)) return fail(c, OMC_EDEVICE, "zero-fill launch failed");
         for (uint64_t done = 0; done < N; done += S) {
             const uint32_t cnt = uint32_t(std::min<uint64_t>(S, N - done));
@@ -1114,16 +1221,15 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
 
 // Sum the per-work-group statistics and read them (and the control words)
 // into L; accumulate adds to what L holds.
-int finish_stats(omc_ctx* c, hipStream_t s, omc_counters& L, bool accumulate)
+int finish_stats(omc_ctx* c, hipStream_t s, omc_counters& L, bool accumulate, const RunMem& M)
 {
     unsigned long long cnts[omc::kNumCounters];
     double en[omc::kNumEnergies];
-    if (omc::launch_stats_reduce(c->d_counters, c->d_energies, omc::kStatsRows, s))
+    if (omc::launch_stats_reduce(M.counters, M.energies, M.rows, s))
         return fail(c, OMC_EDEVICE, "statistics reduce launch failed");
-    HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, c->d_ctrl, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                              s));
-    HIP_TRY(c, hipMemcpyAsync(cnts, c->d_counters, sizeof cnts, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipMemcpyAsync(en, c->d_energies, sizeof en, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctrl, M.ctrl, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(cnts, M.counters, sizeof cnts, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(en, M.energies, sizeof en, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     if (!accumulate) {
         const uint32_t it = L.iterations;
@@ -1154,8 +1260,9 @@ int check_ledger(omc_ctx* c, const omc_counters& L)
 
 template <typename R>
 int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose, double* d_dose2,
-             hipStream_t s)
+             hipStream_t s, RunMem* fixed = nullptr)
 {
+    RunMem M = fixed ? *fixed : ctx_mem(c);
     const omc_params& P = c->prm;
     Job job;
     job.beams.push_back(HostBeam{c->src, &c->edges, &c->cdf, N, h0, &c->psf, c->psf_dev});
@@ -1165,23 +1272,23 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
     job.N = N;
     c->timing = omc_timing{};
     EventTimer tm;
-    tm.on = P.timing != 0;
+    tm.on = P.timing != 0 && !M.fixed;
     tm.s = s;
     RunClock clk;
     clk.start(tm.on, s);
     omc_counters& L = c->last;
     L = omc_counters{};
-    int rc = transport<R>(c, job, seed, s, tm, L);
+    int rc = transport<R>(c, job, seed, s, tm, L, M);
     if (rc == OMC_OK) {
         std::vector<double> nb;
         batch_sizes(N, job.cells, nb);
         tm.begin(3);
-        if (omc::launch_fold(c->d_grid, c->d_rho, c->nvox, job.cells, nb.data(),
+        if (omc::launch_fold(M.grid, c->d_rho, c->nvox, job.cells, nb.data(),
                              c->dx * c->dy * c->dz, double(N), d_dose, d_dose2, s))
             rc = fail(c, OMC_EDEVICE, "fold kernel launch failed");
         tm.end();
         clk.stop(s);
-        if (rc == OMC_OK) rc = finish_stats(c, s, L, false);
+        if (rc == OMC_OK) rc = finish_stats(c, s, L, false, M);
     }
     (void)hipStreamSynchronize(s);
     collect_events(tm.ev, c->timing);
@@ -1322,11 +1429,12 @@ int beamlets_impl(omc_ctx* c, const std::vector<HostBeam>& beams, int particle, 
         job.cell_mode = 1;
         job.cells = gn;
         for (const auto& b : job.beams) job.N += b.n;
-        rc = transport<R>(c, job, seed, s, tm, L);
+        RunMem M = ctx_mem(c);
+        rc = transport<R>(c, job, seed, s, tm, L, M);
         SparsePart part;
         std::vector<uint64_t> grows;
         if (rc == OMC_OK) rc = compact_group(c, job, s, tm, part, grows);
-        if (rc == OMC_OK) rc = finish_stats(c, s, L, g0 > 0);
+        if (rc == OMC_OK) rc = finish_stats(c, s, L, g0 > 0, M);
         if (rc == OMC_OK) {
             const uint64_t base = rows[g0];
             for (int b = 0; b < gn; ++b) rows[g0 + b + 1] = base + grows[b + 1];
@@ -1392,6 +1500,183 @@ int beamlets_impl(omc_ctx* c, const std::vector<HostBeam>& beams, int particle, 
 
 }  // namespace
 
+namespace {
+
+// omc_debug_sample for one transport precision: the samples run on the
+// device in a scratch block of their own (queues for the products, control
+// words, statistics, a one-cell tally, the records), released at the end.
+template <typename R>
+int debug_sample_impl(omc_ctx* c, int which, const double* args, uint32_t seed, uint32_t n,
+                      double* out, uint32_t* words)
+{
+    DeviceTables<R>& T = tables_of(c, R());
+    int rc = device_tables(c, T);
+    if (rc) return rc;
+    const uint64_t waves = (uint64_t(n) + 63) / 64;
+    const uint32_t cap = uint32_t(((2 * uint64_t(n) + 128 * waves + 256) + 63) & ~uint64_t(63));
+    const size_t per = 8 * sizeof(R) + 6 * sizeof(uint32_t);
+    const size_t qbytes = size_t(cap) * per;
+    const size_t bytes = 2 * qbytes + 256 + 256 + 8 * 64 + align256(size_t(n) * omc::kSampleWords *
+                         sizeof(double)) + align256(size_t(n) * sizeof(uint32_t));
+    char* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess)
+        return fail(c, OMC_ENOMEM, "hipMalloc failed for the sampler");
+    char* p = mem;
+    auto take = [&p](size_t k) {
+        char* r = p;
+        p += (k + 255) & ~size_t(255);
+        return r;
+    };
+    omc::QueueView<R> q[2];
+    uint32_t* ctrl = nullptr;
+    char* qmem[2] = {take(qbytes), take(qbytes)};
+    ctrl = reinterpret_cast<uint32_t*>(take(16 * sizeof(uint32_t)));
+    auto* counters = reinterpret_cast<unsigned long long*>(take(omc::kNumCounters * 8));
+    auto* energies = reinterpret_cast<double*>(take(omc::kNumEnergies * 8 + 8 * 8));
+    double* tally = energies + 8;
+    double* d_out = reinterpret_cast<double*>(take(size_t(n) * omc::kSampleWords * sizeof(double)));
+    uint32_t* d_words = reinterpret_cast<uint32_t*>(take(size_t(n) * sizeof(uint32_t)));
+    for (int k = 0; k < 2; ++k) {
+        char* b = qmem[k];
+        auto arr = [&b, cap](size_t elem) {
+            char* r = b;
+            b += size_t(cap) * elem;
+            return r;
+        };
+        q[k].x = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].y = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].z = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].u = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].v = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].w = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].E = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].vox = reinterpret_cast<uint32_t*>(arr(4));
+        q[k].hist = reinterpret_cast<uint32_t*>(arr(4));
+        q[k].qlo = reinterpret_cast<uint32_t*>(arr(4));
+        q[k].qhi = reinterpret_cast<uint32_t*>(arr(4));
+        q[k].tag = reinterpret_cast<uint32_t*>(arr(4));
+        q[k].aux_pos = reinterpret_cast<uint32_t*>(arr(4));
+        q[k].aux_f = reinterpret_cast<R*>(arr(sizeof(R)));
+        q[k].cap = cap;
+        q[k].count = ctrl + 2 * k;
+        q[k].head = ctrl + 2 * k + 1;
+    }
+    auto bail = [&](int code, const std::string& msg) {
+        (void)hipGetLastError();
+        (void)hipFree(mem);
+        return fail(c, code, msg);
+    };
+    if (hipMemset(ctrl, 0, 16 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(counters, 0, omc::kNumCounters * 8) != hipSuccess ||
+        hipMemset(energies, 0, (omc::kNumEnergies + 8) * 8) != hipSuccess ||
+        hipMemset(d_out, 0, size_t(n) * omc::kSampleWords * sizeof(double)) != hipSuccess)
+        return bail(OMC_EDEVICE, "hipMemset failed for the sampler");
+    omc::KernelArgs<R> a = phantom_args(c, T);
+    // every product is kept
+    a.prm.Eabs_e = R(0);
+    a.prm.Eabs_g = R(0);
+    a.prm.kerma = 0;
+    a.tally = {tally, c->nvox};
+    a.stats = {counters, energies, 1u, ctrl + 8, ctrl + 9, ctrl + 10};
+    a.qe_out = q[0];
+    a.qp_out = q[1];
+    int e = 0;
+    if (which == omc::SMP_SOURCE) {
+        Job job;
+        job.beams.push_back(HostBeam{c->src, &c->edges, &c->cdf, n, 0u, &c->psf, c->psf_dev});
+        job.particle = c->src.particle;
+        job.cells = 1;
+        job.N = n;
+        omc::SourceView<R> sv{};
+        if ((rc = pack_sources(c, job, nullptr, sv))) {
+            (void)hipFree(mem);
+            return rc;
+        }
+        c->h_run->seed = seed;
+        c->h_run->n_batches = 1;
+        c->h_run->n_total = n;
+        if (hipMemcpy(c->d_run, c->h_run, sizeof(omc::RunDesc), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return bail(OMC_EDEVICE, "run descriptor upload failed");
+        a.src = sv;
+        a.run = c->d_run;
+        a.src_begin = 0;
+        a.src_count = n;
+        e = omc::Launch<R>::source(a, int((n + 255) / 256), 256, nullptr);
+    } else {
+        omc::SampleArgs sa{which, seed, n, args[0], args[1], args[2], args[3], args[4]};
+        e = omc::Launch<R>::sample(a, sa, d_out, d_words, nullptr);
+    }
+    if (e || hipDeviceSynchronize() != hipSuccess) return bail(OMC_EDEVICE, "sampler launch failed");
+    uint32_t h_ctrl[16];
+    if (hipMemcpy(h_ctrl, ctrl, sizeof h_ctrl, hipMemcpyDeviceToHost) != hipSuccess)
+        return bail(OMC_EDEVICE, "sampler readback failed");
+    if (h_ctrl[8]) return bail(OMC_EQUEUE, "sampler product queue overflow");
+    if (which != omc::SMP_SOURCE &&
+        (hipMemcpy(out, d_out, size_t(n) * omc::kSampleWords * sizeof(double),
+                   hipMemcpyDeviceToHost) != hipSuccess ||
+         hipMemcpy(words, d_words, size_t(n) * sizeof(uint32_t), hipMemcpyDeviceToHost) !=
+             hipSuccess))
+        return bail(OMC_EDEVICE, "sampler readback failed");
+    // the products (or, for the source, the entering particles) from the queues
+    for (int k = 0; k < 2; ++k) {
+        const uint32_t cnt = std::min(h_ctrl[2 * k], cap);
+        if (cnt == 0) continue;
+        std::vector<R> E(cnt), u(cnt), v(cnt), w(cnt), x(cnt), y(cnt), z(cnt);
+        std::vector<uint32_t> hist(cnt), tag(cnt);
+        const std::pair<const void*, void*> cp[] = {
+            {q[k].E, E.data()}, {q[k].u, u.data()}, {q[k].v, v.data()}, {q[k].w, w.data()},
+            {q[k].x, x.data()}, {q[k].y, y.data()}, {q[k].z, z.data()}};
+        for (const auto& pr : cp)
+            if (hipMemcpy(pr.second, pr.first, cnt * sizeof(R), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return bail(OMC_EDEVICE, "sampler readback failed");
+        if (hipMemcpy(hist.data(), q[k].hist, cnt * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(tag.data(), q[k].tag, cnt * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(OMC_EDEVICE, "sampler readback failed");
+        for (uint32_t i = 0; i < cnt; ++i) {
+            if (tag[i] == omc::kHoleTag) continue;
+            if (which == omc::SMP_SOURCE) {
+                if (i >= n) continue;
+                double* r = out + size_t(omc::kSampleWords) * i;
+                r[0] = double(E[i]);
+                r[1] = double(u[i]);
+                r[2] = double(v[i]);
+                r[3] = double(w[i]);
+                r[5] = double(x[i]);
+                r[6] = double(y[i]);
+                r[7] = double(z[i]);
+                r[15] = 1.0;
+                continue;
+            }
+            const uint32_t h = hist[i];
+            if (h >= n) continue;
+            double* r = out + size_t(omc::kSampleWords) * h;
+            const int j = int(r[4]);
+            r[4] = double(j + 1);
+            if (j >= 2) continue;
+            r[5 + 4 * j] = double(E[i]);
+            r[6 + 4 * j] = double(u[i]);
+            r[7 + 4 * j] = double(v[i]);
+            r[8 + 4 * j] = double(w[i]);
+            r[13 + j] = double(tag[i] & 0x7Fu);
+        }
+    }
+    if (which == omc::SMP_SOURCE) {
+        for (uint32_t i = 0; i < n; ++i) words[i] = 4u;
+    } else if (which == omc::SMP_PAIR) {
+        const double K = args[0] - 2.0 * omc::kMC2;
+        for (uint32_t i = 0; i < n; ++i) {
+            double* r = out + size_t(omc::kSampleWords) * i;
+            r[15] = r[4] > 0 ? r[5] / K : 0.0;
+        }
+    }
+    (void)hipFree(mem);
+    return OMC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void omc_default_params(omc_params* p)
@@ -1426,19 +1711,49 @@ int check_phantom(const float* density, const uint8_t* material, size_t nvox, in
                   std::vector<double>& rmax);
 int upload_phantom(omc_ctx* c, const float* density, const uint8_t* material);
 
+// The built-in library (mats == NULL in omc_create): 0 water, 1 lung, 2
+// cortical bone, the three materials of the paper's slab and half-slab
+// phantoms (Sec. 2.2 "Materials"). Mass fractions (normalised), atomic
+// weights in g/mol, I in eV and the nominal density of each; the
+// compositions are ICRU-44-like input data.
+namespace {
+const int kBiZ0[] = {1, 8};
+const double kBiA0[] = {1.008, 15.999};
+const double kBiW0[] = {0.111894, 0.888106};
+const int kBiZ1[] = {1, 6, 7, 8, 11, 15, 16, 17, 19};
+const double kBiA1[] = {1.008, 12.011, 14.007, 15.999, 22.99, 30.974, 32.06, 35.45, 39.098};
+const double kBiW1[] = {0.103, 0.105, 0.031, 0.749, 0.002, 0.002, 0.003, 0.003, 0.002};
+const int kBiZ2[] = {1, 6, 7, 8, 11, 12, 15, 16, 20};
+const double kBiA2[] = {1.008, 12.011, 14.007, 15.999, 22.99, 24.305, 30.974, 32.06, 40.078};
+const double kBiW2[] = {0.03400000000000001, 0.15500000000000003, 0.04200000000000001,
+                        0.43500000000000005, 0.0010000000000000002, 0.0020000000000000005,
+                        0.10300000000000001, 0.0030000000000000005, 0.22500000000000003};
+const omc_material kBuiltin[3] = {{2, kBiZ0, kBiA0, kBiW0, 75.0, 1.0},
+                                  {9, kBiZ1, kBiA1, kBiW1, 75.3, 0.26},
+                                  {9, kBiZ2, kBiA2, kBiW2, 110.0, 1.85}};
+}  // namespace
+
 int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, double dz,
                const float* density, const uint8_t* material, const omc_material* mats,
                int n_mats)
 {
     if (!out) return fail(nullptr, OMC_EINVAL, "out is NULL");
     *out = nullptr;
+    if (!mats) {
+        if (n_mats != 0 && n_mats != 3)
+            return fail(nullptr, OMC_EINVAL, "mats == NULL selects the built-in library of 3 "
+                                             "materials: pass n_mats 0 or 3");
+        mats = kBuiltin;
+        n_mats = 3;
+    }
     if (nx < 1 || ny < 1 || nz < 1 || nx > OMC_MAX_DIM || ny > OMC_MAX_DIM || nz > OMC_MAX_DIM)
         return fail(nullptr, OMC_EINVAL, "phantom dimensions must be in 1..1024");
     if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz))
         return fail(nullptr, OMC_EINVAL, "voxel sizes must be finite and > 0");
     if (!density || !material) return fail(nullptr, OMC_EINVAL, "density/material is NULL");
-    if (n_mats < 1 || n_mats > OMC_MAX_MATERIALS || !mats)
-        return fail(nullptr, OMC_EINVAL, "need 1..8 materials");
+    if (n_mats < 1 || n_mats > OMC_MAX_MATERIALS)
+        return fail(nullptr, OMC_EINVAL, "need 1.." + std::to_string(OMC_MAX_MATERIALS) +
+                                             " materials");
     omc_ctx* c = new (std::nothrow) omc_ctx();
     if (!c) return fail(nullptr, OMC_ENOMEM, "host allocation failed");
     c->nx = nx;
@@ -1694,6 +2009,19 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
     if (p->photon_mode != 0 && p->photon_mode != 1)
         return fail(c, OMC_EINVAL, "photon_mode must be 0 or 1");
     c->prm = *p;
+    return OMC_OK;
+}
+
+int omc_get_geometry(const omc_ctx* c, int* nx, int* ny, int* nz, double* dx, double* dy,
+                     double* dz)
+{
+    if (check_ctx(c)) return fail(nullptr, OMC_EINVAL, "NULL context");
+    if (nx) *nx = c->nx;
+    if (ny) *ny = c->ny;
+    if (nz) *nz = c->nz;
+    if (dx) *dx = c->dx;
+    if (dy) *dy = c->dy;
+    if (dz) *dz = c->dz;
     return OMC_OK;
 }
 
@@ -1965,6 +2293,31 @@ int omc_debug_philox(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_
         rc = fail(nullptr, OMC_EDEVICE, "Philox debug kernel failed");
     (void)hipFree(d);
     return rc;
+}
+
+int omc_debug_sample(omc_ctx* c, int which, const double* args, uint32_t seed, uint32_t n,
+                     double* out, uint32_t* words)
+{
+    if (check_ctx(c) || !out || !words || n == 0 || n > (1u << 22))
+        return fail(c, OMC_EINVAL, "need a context, out and words, and 1 <= n <= 2^22");
+    if (which < omc::SMP_COMPTON || which > omc::SMP_SOURCE)
+        return fail(c, OMC_EINVAL, "unknown sampler");
+    if (which == omc::SMP_SOURCE) {
+        if (!c->has_source) return fail(c, OMC_ESTATE, "omc_set_source must be called first");
+    } else {
+        if (!args) return fail(c, OMC_EINVAL, "NULL args");
+        const double nrm = std::sqrt(args[1] * args[1] + args[2] * args[2] + args[3] * args[3]);
+        if (!(args[0] > 0.0 && args[0] <= omc::kEHi) || !(std::fabs(nrm - 1.0) < 1e-6))
+            return fail(c, OMC_EINVAL, "need 0 < E <= 20 MeV and a unit direction");
+        if (which == omc::SMP_PAIR && !(args[0] > 2.0 * omc::kMC2))
+            return fail(c, OMC_EINVAL, "pair production needs E > 2 mc^2");
+        if (which == omc::SMP_MS && !(args[4] > 0.0 && std::isfinite(args[4])))
+            return fail(c, OMC_EINVAL, "multiple scattering needs x = s / lambda_1 > 0");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::memset(out, 0, size_t(n) * omc::kSampleWords * sizeof(double));
+    return c->prm.parity_fp64 ? debug_sample_impl<double>(c, which, args, seed, n, out, words)
+                              : debug_sample_impl<float>(c, which, args, seed, n, out, words);
 }
 
 int omc_debug_trace(omc_ctx* c, uint32_t seed, uint32_t h, double* out, uint32_t max_records,

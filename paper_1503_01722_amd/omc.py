@@ -23,9 +23,9 @@ EXPORTS = ["omc_default_params", "omc_create", "omc_set_phantom", "omc_set_phant
            "omc_get_phantom",
            "omc_set_source",
            "omc_set_params",
-           "omc_get_params", "omc_run", "omc_run_device", "omc_run_beamlets", "omc_free_sparse",
+           "omc_get_params", "omc_get_geometry", "omc_run", "omc_run_device", "omc_run_beamlets", "omc_free_sparse",
            "omc_autotune", "omc_get_counters", "omc_get_timing", "omc_debug_philox",
-           "omc_debug_trace", "omc_host_tables", "omc_host_ms_table", "omc_last_error",
+           "omc_debug_trace", "omc_debug_sample", "omc_host_tables", "omc_host_ms_table", "omc_last_error",
            "omc_destroy",
            # include/omc_dn.h
            "omc_dn_create", "omc_dn_num_params", "omc_dn_get_params", "omc_dn_set_params",
@@ -148,6 +148,12 @@ def lib():
         L.omc_set_source.argtypes = [vp, C.POINTER(Source)]
         L.omc_set_params.argtypes = [vp, C.POINTER(Params)]
         L.omc_get_params.argtypes = [vp, C.POINTER(Params)]
+        L.omc_debug_sample.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.c_uint32,
+                                       C.c_uint32, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_uint32)]
+        ip = C.POINTER(C.c_int)
+        dp_ = C.POINTER(C.c_double)
+        L.omc_get_geometry.argtypes = [vp, ip, ip, ip, dp_, dp_, dp_]
         L.omc_run.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, dp, dp]
         L.omc_run_device.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp]
         L.omc_run_beamlets.argtypes = [vp, C.POINTER(Beamlet), C.c_int, C.c_uint32, C.c_int, vp,
@@ -232,8 +238,10 @@ class Engine:
         else:
             dens = np.ascontiguousarray(phantom["density"], dtype=np.float32).ravel()
             mat = np.ascontiguousarray(phantom["material"], dtype=np.uint8).ravel()
-        holders = [_MaterialHolder(m) for m in phantom["materials"]]
-        arr = (Material * len(holders))(*[h.struct for h in holders])
+        # materials None: the library's built-in water, lung and bone
+        mats = phantom.get("materials")
+        holders = [_MaterialHolder(m) for m in mats] if mats is not None else []
+        arr = (Material * len(holders))(*[h.struct for h in holders]) if holders else None
         h = C.c_void_p()
         rc = lib().omc_create(C.byref(h), nx, ny, nz, dx, dy, dz,
                               dens.ctypes.data_as(C.POINTER(C.c_float)),
@@ -370,6 +378,28 @@ class Engine:
         _check(lib().omc_debug_trace(self._h, int(seed), int(h), _dptr(out), max_records,
                                      C.byref(n)), self._h)
         return out[: n.value * 12].reshape(n.value, 12)
+
+    SAMPLERS = {"compton": 0, "moller": 1, "brems": 2, "ms": 3, "annihilation": 4, "pair": 5,
+                "source": 6}
+
+    def debug_sample(self, which, args, n, seed=1):
+        """n samples of one interaction on the GPU (omc_debug_sample):
+        (records (n, 16), stream words used (n,))."""
+        a = np.zeros(8)
+        a[: len(args)] = args
+        out = np.zeros(16 * n)
+        words = np.zeros(n, dtype=np.uint32)
+        _check(lib().omc_debug_sample(self._h, self.SAMPLERS[which], _dptr(a), int(seed), int(n),
+                                      _dptr(out), words.ctypes.data_as(C.POINTER(C.c_uint32))),
+               self._h)
+        return out.reshape(n, 16), words
+
+    def geometry(self):
+        """(nx, ny, nz) voxels and (dx, dy, dz) cm of the context's phantom."""
+        n = [C.c_int(0) for _ in range(3)]
+        h = [C.c_double(0) for _ in range(3)]
+        _check(lib().omc_get_geometry(self._h, *[C.byref(v) for v in n + h]), self._h)
+        return tuple(v.value for v in n), tuple(v.value for v in h)
 
     def get_params(self):
         p = Params()

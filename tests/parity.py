@@ -5,7 +5,7 @@ MC2 = 0.51099895
 INT_COUNTERS = ["ph_flights", "ph_fictitious", "ph_compton", "ph_photo", "ph_pair", "ph_cutoff",
                 "ph_escaped", "el_steps", "el_hard_cand", "el_hard_fict", "el_moller", "el_brems",
                 "el_absorbed", "el_escaped", "el_boundary", "el_hinge_trunc", "pos_annihil",
-                "push_ph", "push_el", "src_miss"]
+                "push_ph", "push_el", "src_miss", "watchdog"]
 
 
 def ledger_residual(c):

@@ -181,3 +181,24 @@ def test_struct_layouts_match_header(omc, tmp_path):
         assert got[(cname, "sizeof")] == C.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_builtin_library_arguments(omc):
+    """mats == NULL selects the built-in water/lung/bone library: n_mats must be
+    0 or 3 (checked before any device call), and the material-count error names
+    the real limit."""
+    L = omc.lib()
+    d = np.ones(64, np.float32)
+    m = np.full(64, 2, np.uint8)
+    ctx = C.c_void_p()
+    args = (C.byref(ctx), 4, 4, 4, 0.5, 0.5, 0.5, d.ctypes.data_as(C.POINTER(C.c_float)),
+            m.ctypes.data_as(C.POINTER(C.c_uint8)), None)
+    assert L.omc_create(*args, 5) == omc.OMC_EINVAL and not ctx.value
+    assert b"built-in" in L.omc_last_error(None)
+    m3 = np.full(64, 3, np.uint8)  # id 3 is outside the built-in library
+    assert L.omc_create(C.byref(ctx), 4, 4, 4, 0.5, 0.5, 0.5,
+                        d.ctypes.data_as(C.POINTER(C.c_float)),
+                        m3.ctypes.data_as(C.POINTER(C.c_uint8)), None, 0) == omc.OMC_EINVAL
+    from paper_1503_01722_amd import workloads as W
+    rc, _ = _create(omc, d, np.zeros(64, np.uint8), [W.WATER] * 33)
+    assert rc == omc.OMC_EINVAL and b"1..32" in L.omc_last_error(None)

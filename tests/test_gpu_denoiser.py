@@ -287,3 +287,38 @@ def test_denoise_fallback_is_plain_monte_carlo(omc, W):
     assert not fb2 and err2 == pytest.approx(err, rel=1e-6)
     eng.close()
     net.close()
+
+
+def test_denoise_rejects_mismatched_phantom(omc, W):
+    """An engine whose phantom does not have the network's dimensions, or whose
+    density volume is not a device allocation of the right size, is refused
+    with OMC_EINVAL on the host before any kernel runs (the dose grids the
+    call fills are sized for the network's volume)."""
+    import torch
+    shape = (16, 16, 16)
+    net = omc.Denoiser(shape, seed=2)
+    src = W.photon_beam((6.0, 6.0), (8.0, 8.0), mono_E=2.0)
+    big = W.water_phantom((16, 16, 32), 1.0)
+    eng = omc.Engine(big)
+    eng.set_source(src)
+    n = int(np.prod(shape))
+    d_rho = torch.ones(n, device="cuda")
+    out = torch.zeros(n, device="cuda")
+    with pytest.raises(omc.OmcError) as e:
+        net.denoise(eng, 1000, 1, 0, d_rho, 0.02, 0, out)
+    assert e.value.code == omc.OMC_EINVAL and "dimensions" in str(e.value)
+    eng.close()
+    # the right phantom, but rho in host memory: refused as well
+    eng = omc.Engine(W.water_phantom(shape, 1.0))
+    eng.set_source(src)
+    host_rho = np.ones(n, np.float32)
+    rc = omc.lib().omc_dn_denoise(net._h, eng._h, 1000, 1, 0,
+                                  host_rho.ctypes.data_as(omc.C.c_void_p), 0.02, 0,
+                                  omc.C.c_void_p(out.data_ptr()), omc.C.byref(omc.C.c_double()),
+                                  omc.C.byref(omc.C.c_int()), None)
+    assert rc == omc.OMC_EINVAL
+    # and the checked call still works
+    err, _ = net.denoise(eng, 1000, 1, 0, d_rho, 10.0, 0, out)
+    assert np.isfinite(err)
+    eng.close()
+    net.close()

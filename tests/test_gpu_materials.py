@@ -264,3 +264,23 @@ def test_fp64_library_graph_beamlets_and_phantom_swap(omc, orc, W):
     od2, _, oc2 = orc.run(sp_ph, src, 2500, seed=10)
     assert ints(c2) == ints(oc2)
     np.testing.assert_allclose(d, od2, rtol=1e-6, atol=1e-9 * od2.max())
+
+
+def test_builtin_library_equals_explicit(omc, orc, W):
+    """A context created with mats == NULL holds the built-in water, lung and
+    bone: the FP64 build gives the same event counters as a context given those
+    compositions explicitly, and as the oracle."""
+    ph = W.slab_phantom(32, 1.0)
+    src = W.photon_beam((10.0, 10.0), (16.0, 16.0), spectrum=W.spectrum_6mv())
+    n = 20_000
+    builtin = dict(ph, materials=None)
+    cs = []
+    for p in (builtin, ph):
+        eng = omc.Engine(p)
+        eng.set_source(src)
+        eng.set_params(parity_fp64=1)
+        eng.run(n, seed=6)
+        cs.append(ints(eng.counters()))
+        eng.close()
+    _, _, oc = orc.run(ph, src, n, seed=6)
+    assert cs[0] == cs[1] == ints(oc)

@@ -77,11 +77,28 @@ def _cases(W):
     out["halfslab_small"] = (W.halfslab_phantom(64, 0.5),
                              W.electron_beam(15.0, (10.0, 10.0), (16.0, 16.0), parallel=False),
                              1500, {})
+    # the full 256^3 half-slab of 0.2 cm voxels with its 15 MeV point-source
+    # beam, voxel-limited steps: the largest single-GPU configuration, at a
+    # history count the oracle runs in seconds
+    phf, srcf, _ = W.config("halfslab_e15")
+    out["halfslab_full"] = (phf, srcf, 3000, {})
     return out
 
 
 CASES = ["water_e15", "slab_6mv", "pair_bone", "gantry_ct", "csda", "kerma", "ragged_7", "single",
-         "halfslab_small", "eight_materials"]
+         "halfslab_small", "eight_materials", "halfslab_full"]
+# oracle threads per case: the 256^3 grids are 134 MB per thread and batch
+ORACLE_THREADS = {"halfslab_full": 8}
+
+
+def dose_error(d, od):
+    """Largest FP64-build dose difference from the oracle, relative to the
+    oracle's Dmax and (where the oracle dose is positive) to the voxel dose."""
+    scale = max(float(od.max()), 1e-300)
+    diff = np.abs(d - od)
+    pos = od > 0
+    rel = float(np.max(diff[pos] / od[pos])) if pos.any() else 0.0
+    return float(diff.max()) / scale, rel
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -89,8 +106,11 @@ def test_fp64_parity_counters_identical(omc, orc, W, name):
     ph, src, n, params = _cases(W)[name]
     print(f"[fp64 parity] {name} n={n} shape={ph['shape']}", flush=True)
     d, d2, c = gpu_run(omc, ph, src, n, seed=1, h0=3, parity_fp64=1, **params)
-    od, od2, oc = orc.run(ph, src, n, seed=1, h0=3, params=params)
-    report(name, **{k: c[k] for k in ("el_steps", "ph_flights", "push_el", "push_ph")})
+    od, od2, oc = orc.run(ph, src, n, seed=1, h0=3, params=params,
+                          threads=ORACLE_THREADS.get(name))
+    e_dmax, e_rel = dose_error(d, od)
+    report(name, **{k: c[k] for k in ("el_steps", "ph_flights", "push_el", "push_ph")},
+           dose_err_dmax=f"{e_dmax:.3e}", dose_err_rel=f"{e_rel:.3e}")
     mism = {k: (c[k], oc[k]) for k in INT_COUNTERS if c[k] != oc[k]}
     assert not mism, mism
     assert ledger_residual(c) < 1e-9
@@ -196,7 +216,8 @@ def test_fp32_statistical_parity_vs_oracle(omc, orc, W, name, n_gpu, n_orc):
             assert a == pytest.approx(b, rel=0.02), k
 
 
-@pytest.mark.parametrize("name,n", [("water_e15", 2_000_000), ("slab_6mv", 20_000_000)])
+@pytest.mark.parametrize("name,n", [("water_e15", 2_000_000), ("slab_6mv", 20_000_000),
+                                    ("halfslab_e15", 10_000_000)])
 def test_fp32_vs_fp64_build_high_statistics(omc, W, name, n):
     """The FP32 production build against the FP64 parity build (itself equal to
     the oracle event by event) at statistics the CPU cannot reach, at the bench
