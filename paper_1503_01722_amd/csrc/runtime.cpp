@@ -1618,9 +1618,15 @@ int debug_sample_impl(omc_ctx* c, int which, const double* args, uint32_t seed, 
          hipMemcpy(words, d_words, size_t(n) * sizeof(uint32_t), hipMemcpyDeviceToHost) !=
              hipSuccess))
         return bail(OMC_EDEVICE, "sampler readback failed");
-    // the products (or, for the source, the entering particles) from the queues
+    // the products (or, for the source, the entering particles) from the queues.
+    // The source kernel writes history k to slot k of its particle's queue (a
+    // hole for a ray that misses the phantom) and leaves the count to the
+    // commit kernel of a run, which the sampler does not launch.
+    if (which == omc::SMP_SOURCE) std::memset(out, 0, size_t(n) * omc::kSampleWords * sizeof(double));
+    const int src_q = c->src.particle == 0 ? 1 : 0;
     for (int k = 0; k < 2; ++k) {
-        const uint32_t cnt = std::min(h_ctrl[2 * k], cap);
+        const uint32_t cnt =
+            which == omc::SMP_SOURCE ? (k == src_q ? n : 0u) : std::min(h_ctrl[2 * k], cap);
         if (cnt == 0) continue;
         std::vector<R> E(cnt), u(cnt), v(cnt), w(cnt), x(cnt), y(cnt), z(cnt);
         std::vector<uint32_t> hist(cnt), tag(cnt);

@@ -13,7 +13,7 @@ compositions) through the C ABI against the FP64 CPU oracle.
 import numpy as np
 import pytest
 
-from parity import INT_COUNTERS, ledger_residual
+from parity import INT_COUNTERS, dose_parity, ledger_residual, sparse_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -79,9 +79,7 @@ def test_fp64_library_parity(omc, orc, W, name):
     mism = {k: (c[k], oc[k]) for k in INT_COUNTERS if c[k] != oc[k]}
     assert not mism, mism
     assert ledger_residual(c) < 1e-9
-    scale = max(od.max(), 1e-300)
-    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * scale)
-    np.testing.assert_allclose(d2, od2, rtol=1e-6, atol=1e-9 * scale * scale)
+    dose_parity(d, d2, od, od2, ph["density"], tag=name)
 
 
 @pytest.mark.parametrize("fp64,phantom", [(0, "eight"), (0, "sixteen"), (1, "eight")])
@@ -174,7 +172,7 @@ def test_fp64_parity_on_a_ct_phantom(omc, orc, W):
     report("ct", n_mats=len(np.unique(ref["material"])),
            **{k: c[k] for k in ("el_steps", "ph_flights")})
     assert ints(c) == ints(oc)
-    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * od.max())
+    dose_parity(d, None, od, None, ref["density"], tag="ct")
 
 
 def _hip_runtime():
@@ -252,7 +250,7 @@ def test_fp64_library_graph_beamlets_and_phantom_swap(omc, orc, W):
     nvox = int(np.prod(ph16["shape"]))
     for b, ref in enumerate(od):
         g = sp.row(b, nvox).reshape(ph16["shape"])
-        np.testing.assert_allclose(g, ref, rtol=2e-6, atol=1e-9 * max(ref.max(), 1e-300))
+        sparse_parity(g, ref, tag=f"library beamlet {b}")
     # the same dimensions, three other library materials
     sp_ph = W.layered_phantom(ph16["shape"], 0.5, [(0.0, 8.0, 9, 1.09), (8.0, 14.0, 14, 1.03),
                                                    (14.0, 25.0, 2, 1.85)])
@@ -263,7 +261,7 @@ def test_fp64_library_graph_beamlets_and_phantom_swap(omc, orc, W):
     eng.close()
     od2, _, oc2 = orc.run(sp_ph, src, 2500, seed=10)
     assert ints(c2) == ints(oc2)
-    np.testing.assert_allclose(d, od2, rtol=1e-6, atol=1e-9 * od2.max())
+    dose_parity(d, None, od2, None, sp_ph["density"], tag="phantom swap")
 
 
 def test_builtin_library_equals_explicit(omc, orc, W):

@@ -13,7 +13,7 @@ analytic beam), through the C ABI against the FP64 CPU oracle.
 import numpy as np
 import pytest
 
-from parity import INT_COUNTERS, dose_agreement, ledger_residual
+from parity import INT_COUNTERS, dose_agreement, dose_parity, ledger_residual, sparse_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -78,9 +78,7 @@ def test_fp64_phase_space_counters_identical(omc, orc, W, name):
     assert ledger_residual(c) < 1e-9
     for k in ("E_incident", "E_deposited", "E_escaped"):
         assert c[k] == pytest.approx(oc[k], rel=1e-9, abs=1e-9), k
-    scale = max(od.max(), 1e-300)
-    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * scale)
-    np.testing.assert_allclose(d2, od2, rtol=1e-6, atol=1e-9 * scale * scale)
+    dose_parity(d, d2, od, od2, ph["density"], tag=name)
 
 
 def test_fp64_phase_space_graph_mode(omc, orc, W):
@@ -137,8 +135,7 @@ def test_fp64_beamlets_with_phase_spaces(omc, orc, W, depth):
     for s, refs in ((sp, od), (spe, ode)):
         for b, ref in enumerate(refs):
             g = s.row(b, nvox).reshape(ph["shape"])
-            scale = max(ref.max(), 1e-300)
-            np.testing.assert_allclose(g, ref, rtol=2e-6, atol=1e-9 * scale)
+            sparse_parity(g, ref, tag=f"phase-space beamlet {b}")
 
 
 def test_fp32_vs_fp64_phase_space(omc, W):
@@ -210,8 +207,8 @@ def test_fp64_device_records_parity(omc, orc, W):
     od, _, oc = orc.run(ph, W.psf_source(host), n, seed=7, h0=2)
     report("device_records", **{k: c[k] for k in ("el_steps", "ph_flights", "push_el")})
     assert ints(c) == ints(oc) and ints(c) == ints(hc)
+    dose_parity(d, None, od, None, ph["density"], tag="device records")
     scale = max(od.max(), 1e-300)
-    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * scale)
     np.testing.assert_allclose(d, hd, rtol=1e-12, atol=1e-15 * scale)
 
 
@@ -245,7 +242,7 @@ def test_device_records_graph_and_beamlets(omc, orc, W):
     nvox = int(np.prod(ph["shape"]))
     for b, ref in enumerate(od):
         g = sp.row(b, nvox).reshape(ph["shape"])
-        np.testing.assert_allclose(g, ref, rtol=2e-6, atol=1e-9 * max(ref.max(), 1e-300))
+        sparse_parity(g, ref, tag=f"device-record beamlet {b}")
 
 
 def test_device_records_rejected(omc, W):

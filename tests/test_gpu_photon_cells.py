@@ -11,7 +11,7 @@ ABI against the FP64 CPU oracle taking the same walk.
 import numpy as np
 import pytest
 
-from parity import INT_COUNTERS, dose_agreement, ledger_residual
+from parity import INT_COUNTERS, dose_agreement, dose_parity, ledger_residual
 
 pytestmark = pytest.mark.gpu
 
@@ -72,8 +72,7 @@ def test_fp64_cell_majorant_parity(omc, orc, W, name):
     mism = {k: (c[k], oc[k]) for k in INT_COUNTERS if c[k] != oc[k]}
     assert not mism, mism
     assert ledger_residual(c) < 1e-9
-    scale = max(od.max(), 1e-300)
-    np.testing.assert_allclose(d, od, rtol=1e-6, atol=1e-9 * scale)
+    dose_parity(d, d2, od, od2, ph["density"], tag=name)
 
 
 def test_fp64_cell_majorant_graph_mode(omc, orc, W):

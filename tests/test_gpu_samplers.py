@@ -23,8 +23,9 @@ CASES = {
     "moller": [3.0, *DIR0],
     "moller_thresh": [0.12, *DIR0],
     "brems": [5.0, *DIR0],
-    "ms": [0.0, *DIR0, 0.3],
-    "ms_large": [0.0, *DIR0, 4.0],
+    # the deflection depends on s / lambda_1 only; the energy is not used
+    "ms": [1.0, *DIR0, 0.3],
+    "ms_large": [1.0, *DIR0, 4.0],
     "annihilation": [0.3, *DIR0],
     "pair": [8.0, *DIR0],
 }
