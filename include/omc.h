@@ -266,6 +266,30 @@ int omc_run(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* dose,
 int omc_run_device(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* d_dose,
                    double* d_dose2, void* hip_stream);
 
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * omc_run_device without any device allocation. The run's queues, tally grids,
+ * statistics, control words and source description live in the library's
+ * fixed device scratch, a 128 MiB array that every GPU the library runs on
+ * holds until the process ends; nothing else is allocated or freed.
+ * Results equal omc_run_device's for the same inputs (same streams, same event
+ * counters; dose to summation order). Limits: n_batches x nx*ny*nz <= 6291456
+ * tally doubles (else OMC_EINVAL); the source description (beams and spectra)
+ * within 1 MiB (else OMC_EINVAL); the queues hold about 50000 (FP32) or 27000
+ * (FP64) source histories per chunk, which the call sizes itself. Preconditions:
+ * the physics tables of the context's precision (and the phase-space copy of
+ * a host-record source, and the cell scales for photon_mode 1) are already on
+ * the device: run omc_run or omc_run_device once after omc_create, omc_set_params
+ * or omc_set_source, else OMC_ESTATE. dose and dose2 must each lie inside one
+ * device allocation of the context's device holding nx*ny*nz doubles (else
+ * OMC_EINVAL). Every call on one GPU shares that GPU's scratch, which keeps
+ * the last call's contents (each call clears what must start at zero): calls
+ * that overlap on one GPU, from any context or thread, race and must not be
+ * made. Launched on hip_stream (NULL = default stream) with host-driven
+ * generations; returns when the run is complete on that stream. */
+int omc_run_device_static(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0,
+                          double* d_dose, double* d_dose2, void* hip_stream);
+
 /* One beamlet of a batched run: a source with its own history count and
  * history ids. (The paper transports one beam per run and tunes only the
  * number of work-items per launch, Sec. 2.2.2; batching many small beams into

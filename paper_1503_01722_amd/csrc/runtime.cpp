@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -111,6 +112,7 @@ struct omc_ctx {
     unsigned long long* d_counters = nullptr;
     double* d_energies = nullptr;
     uint32_t* h_ctrl = nullptr;  // pinned readback
+    char* d_scratch = nullptr;   // this device's copy of the fixed scratch array (or NULL)
 
     // host-side tables (FP64) for the current Wcc, kc, Eabs_e
     std::vector<omc::MaterialTables> tabs;
@@ -1683,6 +1685,62 @@ int debug_sample_impl(omc_ctx* c, int which, const double* args, uint32_t seed, 
 
 }  // namespace
 
+// ------------------------------------------------------ fixed device scratch
+// omc_run_device_static runs without allocating device memory: its queues,
+// tally grids, statistics, control words and source description are regions
+// of one file-scope device array. Every GPU the library runs on holds its own
+// copy from module load until the process ends. In host code the array's name
+// is a host-side stand-in, not a device address: the address of each GPU's
+// copy is looked up once per device with hipGetSymbolAddress (at the first
+// omc_create on that device, with the device current), and only that address
+// is passed to kernels and copies.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr uint32_t kScratchRows = 64;  // statistics rows (work-groups share them by index)
+constexpr size_t kScrCtrl = 0;         // 64 control words
+constexpr size_t kScrRun = 256;        // run descriptor
+constexpr size_t kScrCounters = 512;
+constexpr size_t kScrEnergies =
+    kScrCounters + ((size_t(kScratchRows) * omc::kNumCounters * 8 + 255) & ~size_t(255));
+constexpr size_t kScrSrc =
+    kScrEnergies + ((size_t(kScratchRows) * omc::kNumEnergies * 8 + 255) & ~size_t(255));
+constexpr size_t kScrSrcBytes = size_t(1) << 20;   // beams, history prefix, spectra
+constexpr size_t kScrGrid = (kScrSrc + kScrSrcBytes + 255) & ~size_t(255);
+constexpr size_t kScrGridBytes = size_t(48) << 20;  // tally cells: 6291456 doubles
+constexpr size_t kScrQueues = kScrGrid + kScrGridBytes;
+constexpr size_t kScrQueueBytes = kScratchBytes - kScrQueues;  // the four particle queues
+static_assert(kScrQueues % 256 == 0 && kScrQueueBytes > (size_t(64) << 20), "scratch layout");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kScratchDevices] = {};
+bool g_scratch_seen[kScratchDevices] = {};
+
+// The device address of the current device's copy of the scratch array
+// (NULL if the lookup failed); looked up once per device.
+char* scratch_of_device(int device)
+{
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_seen[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[device] = e == hipSuccess ? static_cast<char*>(p) : nullptr;
+        g_scratch_seen[device] = true;
+        (void)hipGetLastError();
+    }
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 extern "C" {
 
 void omc_default_params(omc_params* p)
@@ -1794,6 +1852,9 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
         delete c;
         return fail(nullptr, OMC_EDEVICE, "cannot query the HIP device");
     }
+    // the fixed scratch of this device (omc_run_device_static); a failed
+    // lookup leaves only that entry point unavailable
+    c->d_scratch = scratch_of_device(c->device);
     bool ok = hipMalloc(&c->d_rho, c->nvox * sizeof(float)) == hipSuccess &&
               hipMalloc(&c->d_mat, c->nvox) == hipSuccess &&
               hipMalloc(&c->d_ctrl, 64 * sizeof(uint32_t)) == hipSuccess &&
@@ -2049,6 +2110,43 @@ int omc_run_device(omc_ctx* c, uint64_t n, uint32_t seed, uint32_t h0, double* d
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     return c->prm.parity_fp64 ? run_impl<double>(c, n, seed, h0, d_dose, d_dose2, s)
                               : run_impl<float>(c, n, seed, h0, d_dose, d_dose2, s);
+}
+
+int omc_run_device_static(omc_ctx* c, uint64_t n, uint32_t seed, uint32_t h0, double* d_dose,
+                          double* d_dose2, void* hip_stream)
+{
+    if (check_ctx(c) || !d_dose || !d_dose2) return fail(c, OMC_EINVAL, "NULL argument");
+    if (!c->has_source) return fail(c, OMC_ESTATE, "omc_set_source must be called first");
+    if (n == 0 || uint64_t(h0) + n > (uint64_t(1) << 32))
+        return fail(c, OMC_EINVAL, "need 1 <= n and h0 + n <= 2^32");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (!c->d_scratch)
+        return fail(c, OMC_EDEVICE, "the fixed device scratch is not available on this device");
+    const size_t cells = size_t(c->prm.n_batches) * c->nvox;
+    if (cells > kScrGridBytes / sizeof(double))
+        return fail(c, OMC_EINVAL, "n_batches x voxels exceed the fixed scratch's tally region "
+                                   "(6291456 doubles); use fewer batches or omc_run_device");
+    if (!device_range_ok(c, d_dose, c->nvox * sizeof(double), sizeof(double)) ||
+        !device_range_ok(c, d_dose2, c->nvox * sizeof(double), sizeof(double)))
+        return fail(c, OMC_EINVAL, "dose and dose2 must each be nx*ny*nz doubles of device "
+                                   "memory on the context's device");
+    char* const b = c->d_scratch;
+    RunMem M{};
+    M.ctrl = reinterpret_cast<uint32_t*>(b + kScrCtrl);
+    M.counters = reinterpret_cast<unsigned long long*>(b + kScrCounters);
+    M.energies = reinterpret_cast<double*>(b + kScrEnergies);
+    M.rows = kScratchRows;
+    M.run = reinterpret_cast<omc::RunDesc*>(b + kScrRun);
+    M.grid = reinterpret_cast<double*>(b + kScrGrid);
+    M.fixed = true;
+    M.src = b + kScrSrc;
+    M.src_cap = kScrSrcBytes;
+    M.queues = b + kScrQueues;
+    M.queue_bytes = kScrQueueBytes;
+    M.grid_cap = kScrGridBytes / sizeof(double);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    return c->prm.parity_fp64 ? run_impl<double>(c, n, seed, h0, d_dose, d_dose2, s, &M)
+                              : run_impl<float>(c, n, seed, h0, d_dose, d_dose2, s, &M);
 }
 
 int omc_run(omc_ctx* c, uint64_t n, uint32_t seed, uint32_t h0, double* dose, double* dose2)

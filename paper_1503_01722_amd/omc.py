@@ -23,7 +23,8 @@ EXPORTS = ["omc_default_params", "omc_create", "omc_set_phantom", "omc_set_phant
            "omc_get_phantom",
            "omc_set_source",
            "omc_set_params",
-           "omc_get_params", "omc_get_geometry", "omc_run", "omc_run_device", "omc_run_beamlets", "omc_free_sparse",
+           "omc_get_params", "omc_get_geometry", "omc_run", "omc_run_device",
+           "omc_run_device_static", "omc_run_beamlets", "omc_free_sparse",
            "omc_autotune", "omc_get_counters", "omc_get_timing", "omc_debug_philox",
            "omc_debug_trace", "omc_debug_sample", "omc_host_tables", "omc_host_ms_table", "omc_last_error",
            "omc_destroy",
@@ -156,6 +157,7 @@ def lib():
         L.omc_get_geometry.argtypes = [vp, ip, ip, ip, dp_, dp_, dp_]
         L.omc_run.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, dp, dp]
         L.omc_run_device.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp]
+        L.omc_run_device_static.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp]
         L.omc_run_beamlets.argtypes = [vp, C.POINTER(Beamlet), C.c_int, C.c_uint32, C.c_int, vp,
                                        C.POINTER(SparseOut)]
         L.omc_free_sparse.argtypes = [C.POINTER(SparseOut)]
@@ -342,6 +344,20 @@ class Engine:
         assert dose.numel() == dose2.numel() == int(np.prod(self.shape))
         rc = lib().omc_run_device(self._h, int(n), int(seed), int(h0), C.c_void_p(dose.data_ptr()),
                                   C.c_void_p(dose2.data_ptr()), C.c_void_p(stream.cuda_stream))
+        _check(rc, self._h)
+
+    def run_device_static(self, n, seed, h0, dose, dose2, stream=None):
+        """As run_device, through omc_run_device_static: the run allocates no
+        device memory (the library's fixed scratch; see include/omc.h)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        assert dose.dtype == torch.float64 and dose.is_cuda and dose.is_contiguous()
+        assert dose2.dtype == torch.float64 and dose2.is_cuda and dose2.is_contiguous()
+        assert dose.numel() == dose2.numel() == int(np.prod(self.shape))
+        rc = lib().omc_run_device_static(self._h, int(n), int(seed), int(h0),
+                                         C.c_void_p(dose.data_ptr()), C.c_void_p(dose2.data_ptr()),
+                                         C.c_void_p(stream.cuda_stream))
         _check(rc, self._h)
 
     def run_beamlets(self, beamlets, seed=1, on_device=False, stream=None):
