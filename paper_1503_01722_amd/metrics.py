@@ -6,8 +6,8 @@ dose: for each reference voxel r with D_ref(r) >= thr * max D_ref,
 gamma(r) = min over points r' of sqrt(|r' - r|^2 / dta^2 + (D_ev(r') -
 D_ref(r))^2 / (dd * max D_ref)^2), with D_ev trilinearly interpolated between
 voxel centres. A voxel passes when gamma <= 1, so only points within one DTA
-of r can make it pass: the search samples r' on a grid of `step_mm` inside
-the sphere |r' - r| <= dta. Runs on the GPU with torch.
+of r can make it pass: the search samples r' on a grid of `step_mm` (0.1 mm)
+inside the sphere |r' - r| <= dta. Runs on the GPU with torch.
 """
 import numpy as np
 
@@ -17,47 +17,77 @@ def batch_sigma(dose, dose2, B):
     return np.sqrt(np.maximum(dose2 / B - dose * dose, 0.0) / (B - 1))
 
 
-def gamma_pass_rate(ref, ev, voxel_mm, dd=0.01, dta_mm=1.0, thr=0.1, step_mm=0.2):
+def gamma_offsets(voxel_mm, dta_mm=1.0, step_mm=0.1):
+    """Search offsets of the gamma index: the points of a step_mm grid inside
+    the DTA sphere (the origin excluded), nearest first, in voxel units
+    (z, y, x), with their distance penalty |r' - r|^2 / dta^2."""
+    k = int(np.floor(dta_mm / step_mm + 1e-9))
+    g = np.arange(-k, k + 1) * step_mm
+    oz, oy, ox = np.meshgrid(g, g, g, indexing="ij")
+    r2 = oz ** 2 + oy ** 2 + ox ** 2
+    m = (r2 > 0) & (r2 <= dta_mm ** 2 * (1 + 1e-12))
+    order = np.argsort(r2[m], kind="stable")
+    offs = np.stack([oz[m], oy[m], ox[m]], 1)[order] / np.asarray(voxel_mm, np.float64)
+    return offs, r2[m][order] / dta_mm ** 2
+
+
+def gamma_pass_rate(ref, ev, voxel_mm, dd=0.01, dta_mm=1.0, thr=0.1, step_mm=0.1):
     """Fraction of reference voxels above thr * max(ref) with gamma <= 1.
     ref, ev: arrays (z, y, x) of the same shape (numpy or torch); voxel_mm:
-    voxel sides (z, y, x) in mm."""
+    voxel sides (z, y, x) in mm. D_ev at an offset point is the trilinear
+    interpolant between voxel centres, clamped at the border. Only the
+    pass/fail decision is computed: a voxel leaves the search once some
+    offset makes gamma <= 1, and a voxel that fails has been tried at every
+    offset, so the decision is the exhaustive search's."""
     import torch
-    import torch.nn.functional as F
     dev = "cuda" if torch.cuda.is_available() else "cpu"
-    R = torch.as_tensor(np.asarray(ref, np.float32) if not torch.is_tensor(ref) else ref,
-                        device=dev, dtype=torch.float32)
-    E = torch.as_tensor(np.asarray(ev, np.float32) if not torch.is_tensor(ev) else ev,
-                        device=dev, dtype=torch.float32)
-    R = R.reshape(ref.shape)
-    E = E.reshape(ref.shape)
+
+    def tens(a):
+        t = a if torch.is_tensor(a) else torch.as_tensor(np.asarray(a, np.float32))
+        return t.to(device=dev, dtype=torch.float32).reshape(tuple(np.shape(ref)))
+
+    R, E = tens(ref), tens(ev)
+    n = torch.tensor(R.shape, device=dev, dtype=torch.float32)
     nz, ny, nx = R.shape
     dmax = float(R.max())
-    sel = R >= thr * dmax
     tol = dd * dmax
-    best = ((E - R) / tol) ** 2  # offset 0
-    vz, vy, vx = voxel_mm
-    # sample grid of normalised coordinates for grid_sample (align_corners=True)
-    zs = torch.arange(nz, device=dev, dtype=torch.float32)
-    ys = torch.arange(ny, device=dev, dtype=torch.float32)
-    xs = torch.arange(nx, device=dev, dtype=torch.float32)
-    Zg, Yg, Xg = torch.meshgrid(zs, ys, xs, indexing="ij")
-    E5 = E[None, None]
-    k = int(np.floor(dta_mm / step_mm))
-    for iz in range(-k, k + 1):
-        for iy in range(-k, k + 1):
-            for ix in range(-k, k + 1):
-                r2 = (iz * step_mm) ** 2 + (iy * step_mm) ** 2 + (ix * step_mm) ** 2
-                if r2 > dta_mm ** 2 or r2 == 0:
-                    continue
-                gz = (Zg + iz * step_mm / vz) / max(nz - 1, 1) * 2 - 1
-                gy = (Yg + iy * step_mm / vy) / max(ny - 1, 1) * 2 - 1
-                gx = (Xg + ix * step_mm / vx) / max(nx - 1, 1) * 2 - 1
-                grid = torch.stack([gx, gy, gz], dim=-1)[None]
-                Ei = F.grid_sample(E5, grid, mode="bilinear", padding_mode="border",
-                                   align_corners=True)[0, 0]
-                g2 = ((Ei - R) / tol) ** 2 + r2 / dta_mm ** 2
-                best = torch.minimum(best, g2)
-    return float((best[sel] <= 1.0).float().mean())
+    sel = R >= thr * dmax
+    idx = torch.nonzero(sel).to(torch.float32)  # (N, 3) z, y, x
+    r = R[sel]
+    best = ((E[sel] - r) / tol) ** 2
+    offs, pen = gamma_offsets(voxel_mm, dta_mm, step_mm)
+    Ef = E.reshape(-1)
+    hi = torch.clamp(n - 2, min=0)
+    act = torch.nonzero(best > 1.0).squeeze(1)
+    s = 0
+    while s < len(offs) and act.numel() > 0:
+        b = int(max(1, min(512, 2e7 // act.numel())))
+        o = torch.as_tensor(offs[s:s + b], device=dev, dtype=torch.float32)
+        pb = torch.as_tensor(pen[s:s + b], device=dev, dtype=torch.float32)
+        s += b
+        p = idx[act][:, None, :] + o[None]                    # (na, b, 3)
+        p = torch.minimum(torch.clamp(p, min=0.0), n - 1)
+        p0 = torch.minimum(torch.floor(p), hi)
+        f = p - p0
+        i0 = p0.to(torch.int64)
+        i1 = torch.minimum(i0 + 1, (n - 1).to(torch.int64))
+        zs = (i0[..., 0], i1[..., 0])
+        ys = (i0[..., 1], i1[..., 1])
+        xs = (i0[..., 2], i1[..., 2])
+        fz, fy, fx = f[..., 0], f[..., 1], f[..., 2]
+        val = torch.zeros_like(fz)
+        for cz in (0, 1):
+            wz = fz if cz else 1 - fz
+            for cy in (0, 1):
+                wy = fy if cy else 1 - fy
+                for cx in (0, 1):
+                    wx = fx if cx else 1 - fx
+                    flat = (zs[cz] * ny + ys[cy]) * nx + xs[cx]
+                    val = val + wz * wy * wx * Ef[flat]
+        g2 = ((val - r[act][:, None]) / tol) ** 2 + pb[None]
+        best[act] = torch.minimum(best[act], g2.min(1).values)
+        act = act[best[act] > 1.0]
+    return int((best <= 1.0).sum()) / max(int(best.numel()), 1)
 
 
 def relative_rms(ev, ref, thr=0.1):
