@@ -23,6 +23,7 @@ on one core.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -72,6 +73,10 @@ WORKLOADS = {
     "ceilings": "microbenchmarks of the ceilings: non-packed ALU lane-ops/s (FP32 FMA and "
                 "integer chains), HBM copy bytes/s, FP64 atomic adds/s at random addresses over "
                 "2^14..2^27 doubles and onto 1 or 64 contended addresses",
+    "denoiser_c5": "denoised (1e6 histories + the trained U-Net, omc_dn_denoise) against plain "
+                   "Monte Carlo at equal 1 %/1 mm gamma pass rate, against 1e9-history plain "
+                   "references, on held-out pairs of the denoiser's data set (128^3 CT-like "
+                   "phantoms of 0.25 cm, 6 MV or 15 MeV beams)",
     "denoiser_128": "learned denoiser (4-level U-Net, 16/32/48/64 channels, BF16 matrix cores) "
                     "on 128^3 volumes: one training step (forward, backward, Adam) per step, "
                     "plus the forward (inference) time",
@@ -196,6 +201,45 @@ def roofline_of(kt, units, workload, shape, fixed_steps=False):
             "ops_per_launch": ops / launches}
 
 
+# Energy deposits of the method per event: every electron step deposits its
+# CSDA loss, and an electron absorbed below E_abs, a photoelectric absorption
+# and a photon below its cut-off deposit what they carry. In the paper's
+# method each deposit is one atomic add to the dose counter.
+DEPOSITS = ("el_steps", "el_absorbed", "ph_photo", "ph_cutoff")
+
+
+def atomic_ceiling(footprint, reps=3):
+    """FP64 atomic adds/s at uniform random addresses over `footprint` doubles
+    (the ceilings microbenchmark, libomc_ceilings.so)."""
+    import ctypes as C
+    L = C.CDLL(os.path.join(ROOT, "paper_1503_01722_amd", "_lib", "libomc_ceilings.so"))
+    L.omc_ceil_atomic.argtypes = [C.c_int, C.c_uint32, C.c_uint32, C.c_int, C.c_int,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    ms, work = C.c_double(), C.c_double()
+    fp = int(min(max(footprint, 1 << 14), (1 << 31) - 1))
+    if L.omc_ceil_atomic(0, fp, 256 * 256 * 8, 16, reps, C.byref(ms), C.byref(work)) != 0:
+        raise RuntimeError("atomic microbenchmark failed")
+    return work.value / (ms.value / 1e3), fp
+
+
+def tally_roofline(kt, units, footprint):
+    """The dose tally against the FP64 atomic ceiling: the method's deposits
+    during the transport kernels (photon + electron HIP-event time) over that
+    time, as a fraction of the measured atomic rate at random addresses over the
+    grid footprint the run touched. The per-lane merge of consecutive deposits
+    into one cell issues fewer atomics than deposits, so the fraction can
+    exceed 1."""
+    deposits = sum(units.get(k, 0) for k in DEPOSITS)
+    t = (kt["photon"][0] + kt["electron"][0]) / 1e3
+    ceiling, fp = atomic_ceiling(footprint)
+    achieved = deposits / t if t > 0 else 0.0
+    return {"bound": "fp64_atomic", "kernels": "photon_kernel + electron_kernel",
+            "deposits": deposits, "transport_ms": 1e3 * t, "achieved": achieved,
+            "peak": ceiling, "unit": "deposits/s", "frac": achieved / ceiling,
+            "ceiling": f"FP64 atomic adds at random addresses over {fp} doubles "
+                       "(the run's non-zero voxels x tally cells), measured in this run"}
+
+
 def cpu_baseline_beamlets(ph, job, target_s, threads):
     """The oracle on a bounded sample of the batched workload: whole beamlets,
     each at a reduced history count, every 16th beamlet (all gantry angles)."""
@@ -266,6 +310,109 @@ def bench_denoiser(args, omc, torch, np):
     print(json.dumps(res), flush=True)
 
 
+def bench_denoiser_c5(args, omc, torch, np):
+    """Denoised against plain Monte Carlo at equal gamma pass rate, on held-out
+    pairs of the denoiser's data set (pair ids from 1800, never trained on):
+    per case, a plain reference of 1e9 histories; the denoised path timed as
+    one omc_dn_denoise call (a 1e6-history run, inference, the error estimate
+    and, above 2 %, a 1e8-history plain run as fallback) with the committed
+    weights; P* its gamma pass rate (1 %/1 mm global, 10 % threshold, 0.1 mm
+    search) against the reference; then the fewest plain histories whose dose
+    reaches P* (bisection in log N over [1e6, 4e8]) and the time of that plain
+    run. Each timed run follows an untimed run of the same size and shape.
+    value: the median over the cases of t(plain at P*) / t(denoised)."""
+    from paper_1503_01722_amd import metrics, workloads as W
+    shape = (128, 128, 128)
+    h = 0.25
+    vox_mm = (10 * h,) * 3
+    nv = int(np.prod(shape))
+    n_low, n_ref, n_max, n_fb = 1_000_000, 1_000_000_000, 400_000_000, 100_000_000
+    net = omc.Denoiser(shape)
+    net.set_params(np.load(os.path.join(ROOT, "paper_1503_01722_amd", "weights",
+                                        "denoiser_c5_128.npy")))
+    low_shape = {"blocks_per_cu": 2, "graph_depth": 3}
+    plain_shape = {"blocks_per_cu": 8, "graph_depth": 4}
+    d = torch.zeros(nv, dtype=torch.float64, device="cuda")
+    d2 = torch.zeros_like(d)
+    out = torch.zeros(nv, device="cuda")
+    rows = []
+    t_start = time.perf_counter()
+    for i in range(1800, 1800 + args.cases):
+        ph_seed, src, _ = W.denoiser_pair(i, shape, h)
+        ph = W.ellipsoid_phantom_gpu(shape, h, 12, ph_seed)
+        rho = torch.as_tensor(np.ascontiguousarray(ph["density"], np.float32).ravel(),
+                              device="cuda")
+        eng = omc.Engine(ph)
+        eng.set_source(src)
+
+        def plain(n, seed, timed=False):
+            eng.set_params(**plain_shape)
+            if timed:
+                eng.run_device(n, seed + 1, 0, d, d2)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eng.run_device(n, seed, 0, d, d2)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t, d.float().reshape(shape).clone()
+
+        _, ref = plain(n_ref, 10_000 + i)
+        eng.set_params(**low_shape)
+        net.denoise(eng, n_low, 20_000 + i, 0, rho, 0.02, n_fb, out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        err, fb = net.denoise(eng, n_low, 30_000 + i, 0, rho, 0.02, n_fb, out)
+        torch.cuda.synchronize()
+        t_dn = time.perf_counter() - t
+        p_star = metrics.gamma_pass_rate(ref, out.reshape(shape), vox_mm)
+        lo_n, hi_n = n_low, n_max
+        _, dm = plain(hi_n, 40_000 + i)
+        reached = metrics.gamma_pass_rate(ref, dm, vox_mm) >= p_star
+        if reached:
+            for _ in range(8):
+                mid = int(round(math.sqrt(lo_n * hi_n)))
+                _, dm = plain(mid, 40_000 + i)
+                if metrics.gamma_pass_rate(ref, dm, vox_mm) >= p_star:
+                    hi_n = mid
+                else:
+                    lo_n = mid
+        t_pl, dm = plain(hi_n, 40_000 + i, timed=True)
+        row = {"pair": i, "beam": "6MV" if src["particle"] == 0 else "15MeV_e",
+               "gamma_denoised": p_star,
+               "gamma_low_plain": metrics.gamma_pass_rate(ref, plain(n_low, 50_000 + i)[1],
+                                                          vox_mm),
+               "err_estimate": err, "fallback": fb, "t_denoised_ms": 1e3 * t_dn,
+               "n_plain_equal_gamma": hi_n if reached else None,
+               "t_plain_equal_gamma_ms": 1e3 * t_pl,
+               "speedup": (t_pl / t_dn) if reached else None,
+               "speedup_lower_bound": None if reached else t_pl / t_dn}
+        rows.append(row)
+        eng.close()
+        print("[denoiser_c5] " + json.dumps(row), file=sys.stderr, flush=True)
+    net.close()
+    sp = np.array([r["speedup"] if r["speedup"] is not None else r["speedup_lower_bound"]
+                   for r in rows])
+    q = np.percentile(sp, [0, 25, 50, 75, 100])
+    res = {"metric": "denoised vs plain time at 1%/1mm gamma", "value": float(q[2]),
+           "unit": "x (plain MC time / denoised time, median over cases)", "n_gpus": 1,
+           "steps": args.cases, "warmup": 0,
+           "ms_per_step": float(np.median([r["t_denoised_ms"] for r in rows])),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": "denoiser_c5", "description": WORKLOADS["denoiser_c5"],
+                      "cases": args.cases, "n_low": n_low, "n_reference": n_ref,
+                      "n_fallback": n_fb, "gamma": "1 %/1 mm global, 10 % threshold, 0.1 mm "
+                      "search, trilinear", "weights": "paper_1503_01722_amd/weights/"
+                      "denoiser_c5_128.npy"},
+           "speedup_spread": {"min": q[0], "q25": q[1], "median": q[2], "q75": q[3],
+                              "max": q[4]},
+           "cases_with_plain_beyond_4e8": int(sum(r["speedup"] is None for r in rows)),
+           "fallbacks": int(sum(bool(r["fallback"]) for r in rows)),
+           "gamma_denoised_median": float(np.median([r["gamma_denoised"] for r in rows])),
+           "gamma_low_plain_median": float(np.median([r["gamma_low_plain"] for r in rows])),
+           "wall_s": time.perf_counter() - t_start, "cases": rows}
+    print(json.dumps(res), flush=True)
+
+
 def measure_ceilings(footprints=(1 << 14, 1 << 20, 1 << 24, 1 << 27)):
     """The MI355X ceilings the roofline fractions are taken against, measured
     with the microbenchmarks of libomc_ceilings.so: the non-packed ALU rate
@@ -326,6 +473,12 @@ def main():
     ap.add_argument("--electron-mode", type=int, default=0,
                     help="0: voxel-limited electron steps (the method); 1: fixed steps "
                          "across voxels (the gDPM scheme it is compared with)")
+    ap.add_argument("--cases", type=int, default=20,
+                    help="denoiser_c5: held-out pairs evaluated")
+    ap.add_argument("--tally-copies", type=int, default=0,
+                    help="private copies of each batch's dose grid (1, 2, 4, 8, 16)")
+    ap.add_argument("--source-order", type=int, default=-1,
+                    help="0: source particles in history order; 1: descending energy groups")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape with omc_autotune before the warm-up")
     ap.add_argument("--no-timing-pass", action="store_true",
@@ -361,6 +514,9 @@ def main():
     if args.workload == "denoiser_128":
         bench_denoiser(args, omc, torch, np)
         return
+    if args.workload == "denoiser_c5":
+        bench_denoiser_c5(args, omc, torch, np)
+        return
     if args.workload == "ceilings":
         print(json.dumps({"metric": "ceilings", "config": {"workload": "ceilings",
                                                            "description": WORKLOADS["ceilings"]},
@@ -393,6 +549,10 @@ def main():
         shape["table_mode"] = args.table_mode
     if args.photon_mode:
         shape["photon_mode"] = args.photon_mode
+    if args.tally_copies:
+        shape["tally_copies"] = args.tally_copies
+    if args.source_order >= 0:
+        shape["source_order"] = args.source_order
     eng = omc.Engine(ph)
     eng.set_source(src)
     eng.set_params(parity_fp64=int(args.parity_fp64), **shape)
@@ -449,7 +609,8 @@ def main():
                                          else "phantom majorant"),
                       "launch": {k: params[k] for k in ("block_size", "blocks_per_cu",
                                                         "chunk_histories", "graph_depth",
-                                                        "queue_factor", "straggler_lanes")}}}
+                                                        "queue_factor", "straggler_lanes",
+                                                        "tally_copies", "source_order")}}}
     if not beamlets:
         # time to 1 % sigma at Dmax from the last step's batch estimate
         d = dose.cpu().numpy()
@@ -487,6 +648,8 @@ def main():
                                          "graph_depth")}
         out["roofline"] = roofline_of(kt, units, args.workload, launch,
                                       fixed_steps=args.electron_mode == 1)
+        if not beamlets:
+            out["tally"] = tally_roofline(kt, units, int(np.count_nonzero(d)) * B)
     out["max_steps_per_particle"] = c["max_steps"]
     out["watchdog"] = c["watchdog"]
     if not args.no_cpu_baseline and not beamlets:

@@ -160,6 +160,23 @@ typedef struct {
                                 majorant over the energy nodes, rounded up to 255ths; a
                                 flight spends its optical depth -ln u cell by cell, and a
                                 candidate is accepted with rho mu / mu_cell (0) */
+    int tally_copies;        /* private copies of each batch's FP64 dose grid in a plain run
+                                (1, 2, 4, 8 or 16): history h and its secondaries add their
+                                deposits (Sec. 2.2.2: atomic additions to the dose counter)
+                                into copy h mod tally_copies, and the fold sums the copies
+                                before the batch statistics. Spreads the atomics on the few
+                                hot voxels of a narrow beam over as many addresses; costs
+                                tally_copies x the grid memory. Batched beamlets keep one
+                                copy. Results do not depend on it (1) */
+    int source_order;        /* 0: a source chunk's particles enter the photon or electron
+                                queue in history order; 1: in descending energy groups
+                                (quarter octaves), the paper's simulation of the source
+                                energy bin by energy bin (Sec. 2.2.1, Table 1) without a
+                                drain between bins: waves running together carry particles
+                                of similar energy, the long-lived high-energy ones first.
+                                Applies to spectra and phase spaces. Each particle's
+                                transport depends on its own stream only, so counters are
+                                unchanged and the dose only sums in another order (0) */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */
@@ -253,14 +270,23 @@ int omc_get_geometry(const omc_ctx* ctx, int* nx, int* ny, int* nz, double* dx, 
 /* The context's current parameters (after omc_autotune, the tuned ones). */
 int omc_get_params(const omc_ctx* ctx, omc_params* out);
 
-/* Transport histories h0 .. h0+n-1 with streams keyed by (seed, h) and write
- * dose (MeV/g per history) and dose2 = sum over batches of the squared batch
- * dose, both nx*ny*nz doubles in caller-owned host memory. h0 + n <= 2^32.
- * Blocks until done. */
+/* Transport histories h0 .. h0+n-1 (Sec. 2.1: each source particle and all
+ * its secondaries, photons and electrons coupled, to absorption or escape;
+ * Sec. 2.2.1, Table 1: the whole source simulated) with streams keyed by
+ * (seed, h), and write dose in MeV/g per source history (the unit of Sec. 2.2
+ * "Materials") and dose2 = sum over the n_batches batches of the squared batch
+ * dose, from which the per-voxel uncertainty sigma_D of Sec. 3.1 follows as
+ * sqrt((dose2 / B - dose^2) / (B - 1)); both nx*ny*nz doubles in caller-owned
+ * host memory. h0 + n <= 2^32. Blocks until done. Errors: OMC_EINVAL (NULL
+ * output, n == 0, h0 + n > 2^32), OMC_ESTATE without a source, OMC_EQUEUE,
+ * OMC_ENOMEM, OMC_EDEVICE; OMC_ENUMERIC when the energy ledger (incident +
+ * annihilation rest energy - pair rest energy = deposited + escaped) is off by
+ * more than 1e-9 relative (the dose is still written). */
 int omc_run(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* dose,
             double* dose2);
 
-/* As omc_run, with dose and dose2 in caller-owned device memory, launched on
+/* As omc_run (Sec. 2.1 transport; dose and sigma_D as above), with dose and
+ * dose2 in caller-owned device memory, launched on
  * hip_stream (a hipStream_t; NULL = default stream). Returns when the run is
  * complete on that stream. */
 int omc_run_device(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double* d_dose,
@@ -273,7 +299,7 @@ int omc_run_device(omc_ctx* ctx, uint64_t n, uint32_t seed, uint32_t h0, double*
  * fixed device scratch, a 128 MiB array that every GPU the library runs on
  * holds until the process ends; nothing else is allocated or freed.
  * Results equal omc_run_device's for the same inputs (same streams, same event
- * counters; dose to summation order). Limits: n_batches x nx*ny*nz <= 6291456
+ * counters; dose to summation order). Limits: n_batches x tally_copies x nx*ny*nz <= 6291456
  * tally doubles (else OMC_EINVAL); the source description (beams and spectra)
  * within 1 MiB (else OMC_EINVAL); the queues hold about 50000 (FP32) or 27000
  * (FP64) source histories per chunk, which the call sizes itself. Preconditions:
@@ -334,7 +360,10 @@ void omc_free_sparse(omc_sparse_out* out);
 /* Launch-shape autotuner (the paper sets its number of work-items M by hand,
  * Sec. 2.2.2). Times runs of n_probe histories of the current source with the
  * current physics parameters over work-group size, work-groups per CU, source
- * chunk size and graph depth, keeps the fastest, sizes queue_factor from the
+ * chunk size and graph depth, then tally_copies 2, 4 and 8 on the fastest
+ * shape (while the copies take at most a quarter of the free device memory)
+ * and, for a spectrum or phase-space source, the other source_order; keeps
+ * the fastest, sizes queue_factor from the
  * queue high-water marks it saw, and applies the result to ctx (as
  * omc_set_params would). *best receives it when best != NULL. Each candidate
  * runs three times (the first builds its graph). Errors: OMC_ESTATE without a
@@ -342,10 +371,17 @@ void omc_free_sparse(omc_sparse_out* out);
  * completes. */
 int omc_autotune(omc_ctx* ctx, uint64_t n_probe, uint32_t seed, omc_params* best);
 
+/* The event counters and energy ledger of the last run (the interactions of
+ * Sec. 2.1 by type, the secondaries pushed onto the stacks of Sec. 2.2.1 and
+ * the energies of the ledger), copied to *out. Errors: OMC_EINVAL for NULL. */
 int omc_get_counters(const omc_ctx* ctx, omc_counters* out);
+/* Per-kernel HIP-event times of the last run (see omc_timing; no passage of
+ * the paper: measurement). Errors: OMC_EINVAL for NULL. */
 int omc_get_timing(const omc_ctx* ctx, omc_timing* out);
 
-/* Words of the Philox4x32-10 stream keyed by (seed, h) for particle id q,
+/* Random numbers (Sec. 2.2.3 gives every work-item its own stream; here a
+ * counter-based generator keyed by history instead of RANECU seeded per
+ * work-item). Words of the Philox4x32-10 stream keyed by (seed, h) for particle id q,
  * blocks n0 .. n0+nblocks-1, computed on the GPU: out holds 4*nblocks words
  * (host memory, caller-owned). */
 int omc_debug_philox(uint32_t seed, uint32_t h, uint64_t q, uint32_t n0, uint32_t nblocks,
@@ -396,6 +432,9 @@ int omc_host_ms_table(double* out);
 /* Last error message of ctx (or of the calling thread when ctx is NULL). */
 const char* omc_last_error(const omc_ctx* ctx);
 
+/* Release the context and every device and host allocation it owns (no
+ * passage of the paper: resource management). NULL is ignored. Sparse outputs
+ * of omc_run_beamlets are the caller's and stay valid until omc_free_sparse. */
 void omc_destroy(omc_ctx* ctx);
 
 #ifdef __cplusplus

@@ -14,9 +14,10 @@
 //               tag u32 (type | resumed 0x80 | tally cell << 8), and for
 //               particles set aside mid-track their stream position u32 and
 //               one R of step state; a control block of {count, head} per queue
-//   tally       one f64[nvox] grid per tally cell (the one FP64 step on the
-//               GPU): a cell is a batch of a plain run or a beamlet of a
-//               batched-beamlet run
+//   tally       f64[cells][copies][nvox] (the one FP64 step on the GPU): a
+//               cell is a batch of a plain run or a beamlet of a batched-beamlet
+//               run; a plain run may keep several private copies of each batch
+//               (tally_copies), history h adding into copy h mod copies
 //   sources     BeamSrc[n_beams], history prefix u64[n_beams + 1], spectra
 //   counters    u64[kNumCounters] and f64 energies[kNumEnergies]
 // R is float for production transport and double for the parity build.
@@ -125,8 +126,10 @@ struct ParamView {
 };
 
 struct TallyView {
-    double* grid;        // [cells][nvox]
+    double* grid;        // [cells][copies][nvox]: a particle adds into grid[cell * nvox + v]
     size_t nvox;
+    uint32_t copy_mask;  // copies - 1 (copies a power of two); the source sets a
+                         // history's cell to batch * copies + (h & copy_mask)
 };
 
 // Values that change from run to run, read by the kernels from device memory
@@ -208,6 +211,10 @@ struct KernelArgs {
     const RunDesc* run;
     uint64_t src_begin;   // first job history of this source chunk
     uint32_t src_count;
+    // source order (Sec. 2.2.1, Table 1: source particles are simulated energy
+    // bin by energy bin): [kSrcGroups] particles per energy group, then
+    // [kSrcGroups] each group's next slot; NULL: history order
+    uint32_t* src_order;
     int chunk;            // records a wave takes from the input queue at once
     int min_grid;         // fewest work-groups a transport generation keeps
     int spill_lanes;      // a wave with at most this many live lanes left sets them aside (0: off)
@@ -250,11 +257,22 @@ struct SampleArgs {
     double x;           // multiple scattering: s / lambda_1 of the step
 };
 
+// Energy groups of the ordered source: quarter octaves of the FP32 energy
+// (its bit pattern shifted right by 21: exponent and two mantissa bits, a
+// monotone integer function), group 0 the highest; 0.01-20 MeV spans 44.
+constexpr int kSrcGroups = 64;
+constexpr int kSrcOrderItems = 16;  // histories per work-item of the ordered source passes
+constexpr uint32_t kSrcGroupLo = 0x3C23D70Au >> 21;  // FP32 bits of 0.01 MeV
+
 // Host-side launchers (one instantiation per precision).
 template <typename R>
 struct Launch {
     static int prepare(size_t lds_ph, size_t lds_el, bool gtab);
+    // one work-item per history, or (a.src_order) per kSrcOrderItems histories
     static int source(const KernelArgs<R>& a, int grid, int block, void* stream);
+    // particles per energy group of the chunk (ordered source): into a.src_order;
+    // kSrcOrderItems histories per work-item
+    static int source_groups(const KernelArgs<R>& a, int grid, void* stream);
     // cells: flights with a majorant per macro cell (photon_mode 1)
     static int photon(const KernelArgs<R>& a, int grid, int block, size_t lds, bool gtab,
                       bool cells, void* stream);
@@ -265,9 +283,13 @@ struct Launch {
                       uint32_t* words, void* stream);
 };
 
-int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,
-                double V, double n_total, double* dose, double* dose2, void* stream);
+// grid [B][copies][nvox]: the copies of a batch are summed (in order) first
+int launch_fold(const double* grid, const float* rho, size_t nvox, int B, int copies,
+                const double* nb, double V, double n_total, double* dose, double* dose2,
+                void* stream);
 int launch_queue_reset(uint32_t* ctrl, int which_mask, void* stream);
+// ordered source: cursor[g] = sum of counts[g'] for g' < g, then counts zeroed
+int launch_source_scan(uint32_t* order, void* stream);
 // count of queue `which` += add (appends a source chunk written past the
 // records already waiting in that queue)
 int launch_queue_commit(uint32_t* ctrl, int which, uint32_t add, void* stream);

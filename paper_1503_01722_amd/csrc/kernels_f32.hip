@@ -8,14 +8,15 @@ namespace omc {
 template struct Launch<float>;
 
 // dose_v = sum_b E_vb / (rho_v V N); dose2_v = sum_b (E_vb / (rho_v V N_b))^2,
-// batches in order (Sec. 3.1 reports sigma_D per voxel; batch method).
+// batches in order (Sec. 3.1 reports sigma_D per voxel; batch method); E_vb is
+// the sum, in order, of the batch's private copies.
 struct BatchSizes {
     double nb[64];
 };
 
 __global__ void __launch_bounds__(256)
 fold_kernel(const double* __restrict__ grid, const float* __restrict__ rho, size_t nvox, int B,
-            BatchSizes nbs, double V, double N, double* __restrict__ dose,
+            int K, BatchSizes nbs, double V, double N, double* __restrict__ dose,
             double* __restrict__ dose2)
 {
     const size_t stride = size_t(gridDim.x) * blockDim.x;
@@ -24,7 +25,9 @@ fold_kernel(const double* __restrict__ grid, const float* __restrict__ rho, size
         double d = 0.0, d2 = 0.0;
         for (int b = 0; b < B; ++b) {
             if (!(nbs.nb[b] > 0.0)) continue;
-            const double e = grid[size_t(b) * nvox + v];
+            const double* g = grid + size_t(b) * size_t(K) * nvox + v;
+            double e = g[0];
+            for (int k = 1; k < K; ++k) e += g[size_t(k) * nvox];
             d += e / (mV * N);
             const double db = e / (mV * nbs.nb[b]);
             d2 += db * db;
@@ -34,17 +37,18 @@ fold_kernel(const double* __restrict__ grid, const float* __restrict__ rho, size
     }
 }
 
-int launch_fold(const double* grid, const float* rho, size_t nvox, int B, const double* nb,
-                double V, double n_total, double* dose, double* dose2, void* stream)
+int launch_fold(const double* grid, const float* rho, size_t nvox, int B, int copies,
+                const double* nb, double V, double n_total, double* dose, double* dose2,
+                void* stream)
 {
-    if (B < 1 || B > 64) return -1;
+    if (B < 1 || B > 64 || copies < 1) return -1;
     BatchSizes nbs{};
     for (int b = 0; b < B; ++b) nbs.nb[b] = nb[b];
     const int block = 256;
     size_t blocks = (nvox + block - 1) / block;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(fold_kernel, dim3(unsigned(blocks)), dim3(block), 0, (hipStream_t)stream,
-                       grid, rho, nvox, B, nbs, V, n_total, dose, dose2);
+                       grid, rho, nvox, B, copies, nbs, V, n_total, dose, dose2);
     return detail::launch_status();
 }
 
@@ -61,6 +65,26 @@ __global__ void queue_reset_kernel(uint32_t* ctrl, int mask)
 int launch_queue_reset(uint32_t* ctrl, int mask, void* stream)
 {
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, ctrl, mask);
+    return detail::launch_status();
+}
+
+// Ordered source: each energy group's first slot after the groups above it
+// (group 0 the highest energies), and the counts cleared for the next chunk.
+__global__ void source_scan_kernel(uint32_t* order)
+{
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0u;
+        for (int g = 0; g < kSrcGroups; ++g) {
+            order[kSrcGroups + g] = acc;
+            acc += order[g];
+            order[g] = 0u;
+        }
+    }
+}
+
+int launch_source_scan(uint32_t* order, void* stream)
+{
+    hipLaunchKernelGGL(source_scan_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, order);
     return detail::launch_status();
 }
 

@@ -16,7 +16,18 @@ inline int launch_status()
 template <typename R>
 int Launch<R>::source(const KernelArgs<R>& a, int grid, int block, void* stream)
 {
-    hipLaunchKernelGGL(source_kernel<R>, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+    if (a.src_order)
+        hipLaunchKernelGGL(source_ordered_kernel<R>, dim3(grid), dim3(block), 0,
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(source_kernel<R>, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+    return detail::launch_status();
+}
+
+template <typename R>
+int Launch<R>::source_groups(const KernelArgs<R>& a, int grid, void* stream)
+{
+    hipLaunchKernelGGL(source_group_kernel<R>, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     return detail::launch_status();
 }
 

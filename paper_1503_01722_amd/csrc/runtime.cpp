@@ -105,6 +105,7 @@ struct omc_ctx {
     size_t psf_cap = 0;         // floats d_psf holds
     bool psf_dirty = true;
     omc::RunDesc* d_run = nullptr;
+    uint32_t* d_order = nullptr;  // [2 kSrcGroups]: ordered source counts and cursors
     omc::RunDesc* h_run = nullptr;  // pinned
     double* d_dose = nullptr;   // fold target of omc_run
     double* d_dose2 = nullptr;
@@ -296,6 +297,26 @@ void range_index(const std::vector<R>& rtab, int nm, DeviceTables<R>& t,
     }
 }
 
+// Ratio of each present material's attenuation per unit density to the
+// photon majorant, largest over the energy nodes (indexed by table slot): a
+// voxel of density rho and slot k attenuates at most rho r[k] times the
+// majorant at any energy (both are interpolated linearly between the same
+// nodes).
+std::vector<double> majorant_ratios(const omc_ctx* c)
+{
+    const int NE = omc::kNE;
+    std::vector<double> mh(NE, 0.0);
+    for (int i = 0; i < NE; ++i)
+        for (int m : c->present) mh[i] = std::max(mh[i], c->rho_max[m] * c->tabs[m].muTot[i]);
+    std::vector<double> r(omc::kMaxMaterials, 0.0);
+    for (size_t k = 0; k < c->present.size(); ++k)
+        for (int i = 0; i < NE; ++i) {
+            const double q = c->tabs[c->present[k]].muTot[i] / mh[i];
+            if (mh[i] > 0.0 && q > r[k]) r[k] = q;
+        }
+    return r;
+}
+
 // Macro cells for the photon majorant per cell (photon_mode 1): the smallest
 // power-of-two side that leaves at most kMaxCells cells; each cell's scale is
 // the largest over its voxels of rho * r_m in 255ths, rounded up, r_m the
@@ -311,16 +332,7 @@ int cell_scales(omc_ctx* c, DeviceTables<R>& t)
         if (size_t(t.cnx) * t.cny * t.cnz <= size_t(omc::kMaxCells)) break;
         t.cshift += 1;
     }
-    const int NE = omc::kNE;
-    std::vector<double> mh(NE, 0.0);
-    for (int i = 0; i < NE; ++i)
-        for (int m : c->present) mh[i] = std::max(mh[i], c->rho_max[m] * c->tabs[m].muTot[i]);
-    std::vector<double> r(omc::kMaxMaterials, 0.0);
-    for (size_t k = 0; k < c->present.size(); ++k)
-        for (int i = 0; i < NE; ++i) {
-            const double q = c->tabs[c->present[k]].muTot[i] / mh[i];
-            if (mh[i] > 0.0 && q > r[k]) r[k] = q;
-        }
+    const std::vector<double> r = majorant_ratios(c);
     if (!t.cellq && hipMalloc(&t.cellq, omc::kMaxCells * sizeof(uint32_t)) != hipSuccess) {
         t.cellq = nullptr;
         return fail(c, OMC_ENOMEM, "hipMalloc failed for the cell scales");
@@ -869,6 +881,7 @@ struct RunMem {
     uint32_t rows;
     omc::RunDesc* run;
     double* grid;                   // tally cells (set by transport for the context's own)
+    uint32_t* order;                // [2 kSrcGroups] ordered source counts and cursors
     bool fixed = false;             // the regions below are given: allocate nothing
     char* src = nullptr;            // source description
     size_t src_cap = 0;
@@ -879,7 +892,8 @@ struct RunMem {
 
 RunMem ctx_mem(omc_ctx* c)
 {
-    return RunMem{c->d_ctrl, c->d_counters, c->d_energies, omc::kStatsRows, c->d_run, c->d_grid};
+    return RunMem{c->d_ctrl,  c->d_counters, c->d_energies, omc::kStatsRows,
+                  c->d_run,   c->d_grid,     c->d_order};
 }
 
 // Four queues of cap records each carved from a fixed region (the layout of
@@ -975,7 +989,10 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         }
     }
     const uint64_t N = job.N;
-    const size_t need = size_t(job.cells) * c->nvox;
+    // private copies of each tally cell (plain runs only: the beamlet
+    // compaction reads one grid per cell)
+    const int K = job.cell_mode ? 1 : P.tally_copies;
+    const size_t need = size_t(job.cells) * size_t(K) * c->nvox;
     omc::QueueView<R> Qv[4];
     uint64_t S;
     int block, tgrid;
@@ -1011,7 +1028,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         if ((rc = ensure_queues(c, Q, uint32_t(std::max<uint64_t>(qcap, S)), uint32_t(qcap))))
             return rc;
         for (int k = 0; k < 4; ++k) Qv[k] = Q.q[k];
-        if (c->grid_cells < size_t(job.cells)) {
+        if (c->grid_cells < size_t(job.cells) * size_t(K)) {
             drop_graph(c);
             dfree(c->d_grid);
             c->grid_cells = 0;
@@ -1019,7 +1036,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
                 c->d_grid = nullptr;
                 return fail(c, OMC_ENOMEM, "hipMalloc failed for the tally grids");
             }
-            c->grid_cells = size_t(job.cells);
+            c->grid_cells = size_t(job.cells) * size_t(K);
         }
         M.grid = c->d_grid;
     }
@@ -1033,7 +1050,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     HIP_TRY(c, hipMemcpyAsync(M.run, c->h_run, sizeof(omc::RunDesc), hipMemcpyHostToDevice, s));
 
     omc::KernelArgs<R> a = phantom_args(c, T);
-    a.tally = {M.grid, c->nvox};
+    a.tally = {M.grid, c->nvox, uint32_t(K - 1)};
     a.stats = {M.counters, M.energies, M.rows, M.ctrl + 8, M.ctrl + 9, M.ctrl + 10};
     a.src = sv;
     a.trace = c->trace;
@@ -1041,6 +1058,12 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     a.chunk = 64;
     a.min_grid = c->cu_count;
     a.spill_lanes = P.straggler_lanes;
+    // the ordered source (Sec. 2.2.1: energy bin by energy bin) where the
+    // particles' energies differ: a spectrum or a phase space
+    bool spread = false;
+    for (const HostBeam& hb : job.beams)
+        spread = spread || hb.src.geometry == 2 || hb.src.n_bins > 0;
+    a.src_order = P.source_order == 1 && spread ? M.order : nullptr;
 
     const int nm = int(c->present.size());
     int lds_max = 0, lds_cu = 0;
@@ -1069,7 +1092,8 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         return omc::launch_zero(M.grid, need, st) ||
                omc::launch_zero(M.counters, size_t(M.rows) * omc::kNumCounters, st) ||
                omc::launch_zero(M.energies, size_t(M.rows) * omc::kNumEnergies, st) ||
-               omc::launch_zero(M.ctrl, 8, st);
+               omc::launch_zero(M.ctrl, 8, st) ||
+               omc::launch_zero(M.order, omc::kSrcGroups, st);
     };
     auto source = [&](uint64_t begin, uint32_t cnt, int pc, int ec, hipStream_t st,
                       EventTimer& t) {
@@ -1078,7 +1102,11 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         a.src_begin = begin;
         a.src_count = cnt;
         t.begin(0);
-        const int e = omc::Launch<R>::source(a, int((cnt + 255) / 256), 256, st);
+        const uint32_t per = a.src_order ? 256u * omc::kSrcOrderItems : 256u;
+        const int grid = int((uint64_t(cnt) + per - 1) / per);
+        const int e = (a.src_order && (omc::Launch<R>::source_groups(a, grid, st) ||
+                                       omc::launch_source_scan(M.order, st))) ||
+                      omc::Launch<R>::source(a, grid, 256, st);
         t.end();
         return e || omc::launch_queue_commit(M.ctrl, job.particle == 0 ? pc : ec, cnt, st);
     };
@@ -1285,7 +1313,7 @@ int run_impl(omc_ctx* c, uint64_t N, uint32_t seed, uint32_t h0, double* d_dose,
         std::vector<double> nb;
         batch_sizes(N, job.cells, nb);
         tm.begin(3);
-        if (omc::launch_fold(M.grid, c->d_rho, c->nvox, job.cells, nb.data(),
+        if (omc::launch_fold(M.grid, c->d_rho, c->nvox, job.cells, P.tally_copies, nb.data(),
                              c->dx * c->dy * c->dz, double(N), d_dose, d_dose2, s))
             rc = fail(c, OMC_EDEVICE, "fold kernel launch failed");
         tm.end();
@@ -1578,7 +1606,7 @@ int debug_sample_impl(omc_ctx* c, int which, const double* args, uint32_t seed, 
     a.prm.Eabs_e = R(0);
     a.prm.Eabs_g = R(0);
     a.prm.kerma = 0;
-    a.tally = {tally, c->nvox};
+    a.tally = {tally, c->nvox, 0u};
     a.stats = {counters, energies, 1u, ctrl + 8, ctrl + 9, ctrl + 10};
     a.qe_out = q[0];
     a.qp_out = q[1];
@@ -1700,7 +1728,9 @@ constexpr size_t kScratchBytes = size_t(128) << 20;
 constexpr uint32_t kScratchRows = 64;  // statistics rows (work-groups share them by index)
 constexpr size_t kScrCtrl = 0;         // 64 control words
 constexpr size_t kScrRun = 256;        // run descriptor
-constexpr size_t kScrCounters = 512;
+constexpr size_t kScrOrder = 512;      // ordered source counts and cursors
+constexpr size_t kScrCounters = 1024;
+static_assert(kScrOrder + 2 * omc::kSrcGroups * sizeof(uint32_t) <= kScrCounters, "layout");
 constexpr size_t kScrEnergies =
     kScrCounters + ((size_t(kScratchRows) * omc::kNumCounters * 8 + 255) & ~size_t(255));
 constexpr size_t kScrSrc =
@@ -1769,6 +1799,8 @@ void omc_default_params(omc_params* p)
     p->electron_mode = 0;
     p->table_mode = 0;
     p->photon_mode = 0;
+    p->tally_copies = 1;
+    p->source_order = 0;
 }
 
 int check_phantom(const float* density, const uint8_t* material, size_t nvox, int n_mats,
@@ -1864,6 +1896,7 @@ int omc_create(omc_ctx** out, int nx, int ny, int nz, double dx, double dy, doub
                                             sizeof(double)) == hipSuccess &&
               hipHostMalloc(&c->h_ctrl, 64 * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc(&c->d_run, sizeof(omc::RunDesc)) == hipSuccess &&
+              hipMalloc(&c->d_order, 2 * omc::kSrcGroups * sizeof(uint32_t)) == hipSuccess &&
               hipHostMalloc(&c->h_run, sizeof(omc::RunDesc)) == hipSuccess;
     ok = ok && hipMalloc(&c->d_vox, c->nvox * 2 * sizeof(uint32_t)) == hipSuccess &&
          hipMalloc(&c->d_slot, omc::kMaxMaterials * sizeof(uint32_t)) == hipSuccess;
@@ -2075,6 +2108,10 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
         return fail(c, OMC_EINVAL, "table_mode must be 0, 1 or 2");
     if (p->photon_mode != 0 && p->photon_mode != 1)
         return fail(c, OMC_EINVAL, "photon_mode must be 0 or 1");
+    if (p->tally_copies < 1 || p->tally_copies > 16 || (p->tally_copies & (p->tally_copies - 1)))
+        return fail(c, OMC_EINVAL, "tally_copies must be 1, 2, 4, 8 or 16");
+    if (p->source_order != 0 && p->source_order != 1)
+        return fail(c, OMC_EINVAL, "source_order must be 0 or 1");
     c->prm = *p;
     return OMC_OK;
 }
@@ -2122,10 +2159,11 @@ int omc_run_device_static(omc_ctx* c, uint64_t n, uint32_t seed, uint32_t h0, do
     HIP_TRY(c, hipSetDevice(c->device));
     if (!c->d_scratch)
         return fail(c, OMC_EDEVICE, "the fixed device scratch is not available on this device");
-    const size_t cells = size_t(c->prm.n_batches) * c->nvox;
+    const size_t cells = size_t(c->prm.n_batches) * size_t(c->prm.tally_copies) * c->nvox;
     if (cells > kScrGridBytes / sizeof(double))
-        return fail(c, OMC_EINVAL, "n_batches x voxels exceed the fixed scratch's tally region "
-                                   "(6291456 doubles); use fewer batches or omc_run_device");
+        return fail(c, OMC_EINVAL, "n_batches x tally_copies x voxels exceed the fixed scratch's "
+                                   "tally region (6291456 doubles); use fewer batches or "
+                                   "omc_run_device");
     if (!device_range_ok(c, d_dose, c->nvox * sizeof(double), sizeof(double)) ||
         !device_range_ok(c, d_dose2, c->nvox * sizeof(double), sizeof(double)))
         return fail(c, OMC_EINVAL, "dose and dose2 must each be nx*ny*nz doubles of device "
@@ -2137,6 +2175,7 @@ int omc_run_device_static(omc_ctx* c, uint64_t n, uint32_t seed, uint32_t h0, do
     M.energies = reinterpret_cast<double*>(b + kScrEnergies);
     M.rows = kScratchRows;
     M.run = reinterpret_cast<omc::RunDesc*>(b + kScrRun);
+    M.order = reinterpret_cast<uint32_t*>(b + kScrOrder);
     M.grid = reinterpret_cast<double*>(b + kScrGrid);
     M.fixed = true;
     M.src = b + kScrSrc;
@@ -2351,6 +2390,38 @@ int omc_autotune(omc_ctx* c, uint64_t n_probe, uint32_t seed, omc_params* best)
             }
         }
     }
+    // private tally copies: they pay where the deposits crowd a few voxels (a
+    // narrow beam); tried on the fastest shape while the grids take at most a
+    // quarter of the free device memory
+    if (top_ms < 1e300) {
+        size_t free_b = 0, total_b = 0;
+        (void)hipMemGetInfo(&free_b, &total_b);
+        (void)hipGetLastError();
+        for (int k : {2, 4, 8}) {
+            const size_t bytes = size_t(base.n_batches) * size_t(k) * c->nvox * sizeof(double);
+            if (bytes > free_b / 4) break;
+            omc_params q = top;
+            q.tally_copies = k;
+            double ms;
+            omc_counters L;
+            if (timed(q, ms, L) != OMC_OK) continue;
+            if (ms < top_ms) {
+                top_ms = ms;
+                top = q;
+            }
+        }
+        // the other source order, where the source energies differ
+        if (c->src.geometry == 2 || c->src.n_bins > 0) {
+            omc_params q = top;
+            q.source_order = 1 - top.source_order;
+            double ms;
+            omc_counters L;
+            if (timed(q, ms, L) == OMC_OK && ms < top_ms) {
+                top_ms = ms;
+                top = q;
+            }
+        }
+    }
     drop_graph(c);
     if (top_ms >= 1e300) {
         c->prm = base;
@@ -2514,6 +2585,7 @@ void omc_destroy(omc_ctx* c)
     dfree(c->d_dose);
     dfree(c->d_dose2);
     dfree(c->d_ctrl);
+    dfree(c->d_order);
     dfree(c->d_counters);
     dfree(c->d_energies);
     if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);

@@ -82,16 +82,27 @@ def _cases(W):
     # history count the oracle runs in seconds
     phf, srcf, _ = W.config("halfslab_e15")
     out["halfslab_full"] = (phf, srcf, 3000, {})
+    # private tally copies (work-group g adds into copy g mod 8): the same
+    # deposits in another summation order
+    out["water_e15_copies8"] = (ph, src, 10_000, {"tally_copies": 8})
+    out["slab_6mv_copies4"] = (ph2, out["slab_6mv"][1], 20_000, {"tally_copies": 4})
+    # the ordered source (descending energy groups): the same particles in
+    # another queue order
+    out["slab_6mv_ordered"] = (ph2, out["slab_6mv"][1], 20_000, {"source_order": 1})
+    out["gantry_ct_ordered"] = (ph4, s4, 20_000, {"source_order": 1, "tally_copies": 2})
     return out
 
 
 CASES = ["water_e15", "slab_6mv", "pair_bone", "gantry_ct", "csda", "kerma", "ragged_7", "single",
-         "halfslab_small", "eight_materials", "halfslab_full"]
+         "halfslab_small", "eight_materials", "halfslab_full", "water_e15_copies8",
+         "slab_6mv_copies4", "slab_6mv_ordered", "gantry_ct_ordered"]
 # oracle threads per case: the 256^3 grids are 134 MB per thread and batch
 ORACLE_THREADS = {"halfslab_full": 8}
 # dose tolerance (fraction of Dmax) where ten times the measured difference
 # exceeds the default of the parity rule
-DOSE_TOLS = {"slab_6mv": 1.5e-8, "pair_bone": 3.5e-9, "halfslab_full": 2e-5}
+DOSE_TOLS = {"slab_6mv": 1.5e-8, "slab_6mv_copies4": 1.5e-8, "slab_6mv_ordered": 1.5e-8,
+             "pair_bone": 3.5e-9,
+             "halfslab_full": 2e-5}
 
 
 def dose_error(d, od):
