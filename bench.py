@@ -17,9 +17,13 @@ with per-beamlet sparse output left in HBM.
 Prints one JSON line: histories/s, time to 1 % sigma at Dmax, the ALU roofline
 of the dominant kernel (algorithmic lane operations per launch over its
 HIP-event launch time, from an instrumented pass of the same steps right after
-the timed region: HIP events cannot time kernels inside a graph) and the CPU
+the timed region: HIP events cannot time kernels inside a graph), the dose
+tally against the FP64 atomic rate measured in the same run, and the CPU
 oracle timed on a bounded sample, on every host core this process may use and
-on one core.
+on one core. --workload denoiser_c5 prints the third metric instead: the time
+of the denoised path against plain Monte Carlo at equal 1 %/1 mm gamma pass
+rate on held-out pairs, against 1e9-history plain references. --workload
+ceilings prints the microbenchmarked ceilings.
 """
 import argparse
 import json
