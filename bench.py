@@ -121,7 +121,8 @@ SHAPES = {
     "layers16_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 4},
     "ct_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
     "water_e15": {"graph_depth": 8, "chunk_histories": 0, "blocks_per_cu": 4},
-    "halfslab_e15": {"graph_depth": 6, "chunk_histories": 0, "blocks_per_cu": 8},
+    "halfslab_e15": {"graph_depth": 6, "chunk_histories": 0, "blocks_per_cu": 8,
+                     "event_lanes": 24},
 }
 
 
@@ -614,7 +615,8 @@ def main():
                       "launch": {k: params[k] for k in ("block_size", "blocks_per_cu",
                                                         "chunk_histories", "graph_depth",
                                                         "queue_factor", "straggler_lanes",
-                                                        "tally_copies", "source_order")}}}
+                                                        "tally_copies", "source_order",
+                                                        "event_lanes")}}}
     if not beamlets:
         # time to 1 % sigma at Dmax from the last step's batch estimate
         d = dose.cpu().numpy()

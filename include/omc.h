@@ -177,6 +177,12 @@ typedef struct {
                                 Applies to spectra and phase spaces. Each particle's
                                 transport depends on its own stream only, so counters are
                                 unchanged and the dose only sums in another order (0) */
+    int event_lanes;         /* an electron step that ends in a hard-event candidate (Sec.
+                                2.1) leaves its lane waiting; the Moller/bremsstrahlung
+                                sampling runs for the waiting lanes of a wave together once
+                                this many wait (1..64) or no lane has a step left. Fewer:
+                                passes with fewer lanes; more: more lanes idle meanwhile.
+                                Results do not depend on it (16) */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */
@@ -361,8 +367,9 @@ void omc_free_sparse(omc_sparse_out* out);
  * Sec. 2.2.2). Times runs of n_probe histories of the current source with the
  * current physics parameters over work-group size, work-groups per CU, source
  * chunk size and graph depth, then tally_copies 2, 4 and 8 on the fastest
- * shape (while the copies take at most a quarter of the free device memory)
- * and, for a spectrum or phase-space source, the other source_order; keeps
+ * shape (while the copies take at most a quarter of the free device memory),
+ * event_lanes 24 and 32 and, for a spectrum or phase-space source, the other
+ * source_order; keeps
  * the fastest, sizes queue_factor from the
  * queue high-water marks it saw, and applies the result to ctx (as
  * omc_set_params would). *best receives it when best != NULL. Each candidate

@@ -218,6 +218,7 @@ struct KernelArgs {
     int chunk;            // records a wave takes from the input queue at once
     int min_grid;         // fewest work-groups a transport generation keeps
     int spill_lanes;      // a wave with at most this many live lanes left sets them aside (0: off)
+    int event_lanes;      // waiting electrons that start a deferred-event pass
 };
 
 // LDS bytes a transport work-group stages: the tables of every material the

@@ -1058,6 +1058,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
     a.chunk = 64;
     a.min_grid = c->cu_count;
     a.spill_lanes = P.straggler_lanes;
+    a.event_lanes = P.event_lanes;
     // the ordered source (Sec. 2.2.1: energy bin by energy bin) where the
     // particles' energies differ: a spectrum or a phase space
     bool spread = false;
@@ -1801,6 +1802,7 @@ void omc_default_params(omc_params* p)
     p->photon_mode = 0;
     p->tally_copies = 1;
     p->source_order = 0;
+    p->event_lanes = 16;
 }
 
 int check_phantom(const float* density, const uint8_t* material, size_t nvox, int n_mats,
@@ -2112,6 +2114,8 @@ int omc_set_params(omc_ctx* c, const omc_params* p)
         return fail(c, OMC_EINVAL, "tally_copies must be 1, 2, 4, 8 or 16");
     if (p->source_order != 0 && p->source_order != 1)
         return fail(c, OMC_EINVAL, "source_order must be 0 or 1");
+    if (p->event_lanes < 1 || p->event_lanes > 64)
+        return fail(c, OMC_EINVAL, "event_lanes must be in 1..64");
     c->prm = *p;
     return OMC_OK;
 }
@@ -2406,6 +2410,17 @@ int omc_autotune(omc_ctx* c, uint64_t n_probe, uint32_t seed, omc_params* best)
             omc_counters L;
             if (timed(q, ms, L) != OMC_OK) continue;
             if (ms < top_ms) {
+                top_ms = ms;
+                top = q;
+            }
+        }
+        // the number of waiting electrons that starts an event pass
+        for (int k : {24, 32}) {
+            omc_params q = top;
+            q.event_lanes = k;
+            double ms;
+            omc_counters L;
+            if (timed(q, ms, L) == OMC_OK && ms < top_ms) {
                 top_ms = ms;
                 top = q;
             }

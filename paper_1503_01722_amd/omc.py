@@ -73,7 +73,8 @@ class Params(C.Structure):
                 ("graph_depth", C.c_int), ("beamlet_group", C.c_int),
                 ("sparse_threshold", C.c_double), ("straggler_lanes", C.c_int),
                 ("electron_mode", C.c_int), ("table_mode", C.c_int), ("photon_mode", C.c_int),
-                ("tally_copies", C.c_int), ("source_order", C.c_int)]
+                ("tally_copies", C.c_int), ("source_order", C.c_int),
+                ("event_lanes", C.c_int)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -90,12 +90,18 @@ def _cases(W):
     # another queue order
     out["slab_6mv_ordered"] = (ph2, out["slab_6mv"][1], 20_000, {"source_order": 1})
     out["gantry_ct_ordered"] = (ph4, s4, 20_000, {"source_order": 1, "tally_copies": 2})
+    # the deferred electron events sampled as soon as one lane waits, or only
+    # when every live lane waits: the same particles, in another lane order
+    out["water_e15_events1"] = (ph, src, 5000, {"event_lanes": 1})
+    out["halfslab_small_events64"] = (out["halfslab_small"][0], out["halfslab_small"][1], 1500,
+                                      {"event_lanes": 64})
     return out
 
 
 CASES = ["water_e15", "slab_6mv", "pair_bone", "gantry_ct", "csda", "kerma", "ragged_7", "single",
          "halfslab_small", "eight_materials", "halfslab_full", "water_e15_copies8",
-         "slab_6mv_copies4", "slab_6mv_ordered", "gantry_ct_ordered"]
+         "slab_6mv_copies4", "slab_6mv_ordered", "gantry_ct_ordered", "water_e15_events1",
+         "halfslab_small_events64"]
 # oracle threads per case: the 256^3 grids are 134 MB per thread and batch
 ORACLE_THREADS = {"halfslab_full": 8}
 # dose tolerance (fraction of Dmax) where ten times the measured difference
