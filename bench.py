@@ -112,8 +112,8 @@ def denoiser_flops(n):
     return fwd, fwd + bwd
 
 # launch shape per workload: graph generations per source chunk, histories per
-# chunk (0 = 2^24), work-groups per CU (what omc_autotune picks on MI355X; the
-# --autotune flag re-runs it)
+# chunk (0 = 2^24), work-groups per CU (what omc_autotune and sweeps of chunk
+# and graph depth picked on MI355X; the --autotune flag re-runs the autotuner)
 SHAPES = {
     "slab_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
     "slab_6mv_psf": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
@@ -121,7 +121,10 @@ SHAPES = {
     "layers16_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 4},
     "ct_6mv": {"graph_depth": 4, "chunk_histories": 0, "blocks_per_cu": 6},
     "water_e15": {"graph_depth": 8, "chunk_histories": 0, "blocks_per_cu": 4},
-    "halfslab_e15": {"graph_depth": 6, "chunk_histories": 0, "blocks_per_cu": 8,
+    # the whole step as one chunk (its queues take about 134 GB of HBM):
+    # 340 against 380 ms per step with 2^24-history chunks, which end every
+    # persistent launch in a tail of long-lived particles six times as often
+    "halfslab_e15": {"graph_depth": 10, "chunk_histories": 100_000_000, "blocks_per_cu": 8,
                      "event_lanes": 24},
 }
 

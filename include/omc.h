@@ -366,7 +366,9 @@ void omc_free_sparse(omc_sparse_out* out);
 /* Launch-shape autotuner (the paper sets its number of work-items M by hand,
  * Sec. 2.2.2). Times runs of n_probe histories of the current source with the
  * current physics parameters over work-group size, work-groups per CU, source
- * chunk size and graph depth, then tally_copies 2, 4 and 8 on the fastest
+ * chunk size (up to 2^24 histories, or up to the whole probe while its queues
+ * take at most half the free device memory) and graph depth, then
+ * tally_copies 2, 4 and 8 on the fastest
  * shape (while the copies take at most a quarter of the free device memory),
  * event_lanes 24 and 32 and, for a spectrum or phase-space source, the other
  * source_order; keeps

@@ -2334,7 +2334,20 @@ int omc_autotune(omc_ctx* c, uint64_t n_probe, uint32_t seed, omc_params* best)
         int block, per_cu;
     };
     const Shape shapes[] = {{256, 2}, {256, 4}, {256, 6}, {256, 8}, {128, 4}, {128, 8}};
-    const uint64_t full = std::min<uint64_t>(n_probe, uint64_t(1) << 24);
+    // the largest chunk tried: the whole probe while its queues (four of them,
+    // at the probing queue factor of 8) take at most half the free device
+    // memory; fewer, longer persistent launches leave fewer tails of
+    // long-lived particles
+    uint64_t full = std::min<uint64_t>(n_probe, uint64_t(1) << 24);
+    {
+        size_t free_b = 0, total_b = 0;
+        (void)hipMemGetInfo(&free_b, &total_b);
+        (void)hipGetLastError();
+        const size_t per = c->prm.parity_fp64 ? 8 * sizeof(double) + 6 * sizeof(uint32_t)
+                                              : 8 * sizeof(float) + 6 * sizeof(uint32_t);
+        const uint64_t fit = uint64_t(free_b / 2 / (4 * 8 * per));
+        full = std::max(full, std::min<uint64_t>(n_probe, std::min<uint64_t>(fit, 0x0fffffffull)));
+    }
     omc_params top = base;
     double top_ms = 1e300;
     uint64_t hwm = 0, hwm_chunk = 1;
