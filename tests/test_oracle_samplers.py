@@ -43,8 +43,10 @@ def test_compton_angle_chi2(orc, E):
     assert np.all(words % 3 == 0) and words.min() == 3
 
 
-@pytest.mark.parametrize("T", [0.3, 2.0, 15.0])
-def test_moller_chi2(orc, T):
+def moller_pvalue(orc, T, n=200_000):
+    """chi-square p-value of the oracle's Moller eps = W/T samples against the
+    Moller cross section differential in eps, integrated by quadrature; 0 if a
+    sample leaves [Wcc/T, 1/2]."""
     Wcc = 0.05
     e0 = Wcc / T
     tau = T / MC2
@@ -52,12 +54,51 @@ def test_moller_chi2(orc, T):
     a2 = (tau / g) ** 2
     b = (2 * tau + 1) / g**2
     pdf = lambda e: 1 / e**2 + 1 / (1 - e) ** 2 + a2 - b / (e * (1 - e))
-    s = orc.sample_moller(T, Wcc, 200_000, seed=5)
-    assert s.min() >= e0 and s.max() <= 0.5
+    s = orc.sample_moller(T, Wcc, n, seed=5)
+    if s.min() < e0 or s.max() > 0.5:
+        return 0.0
     edges = np.geomspace(e0, 0.5, 41)
     probs = np.array([integrate.quad(pdf, lo, hi, epsabs=0, epsrel=1e-10)[0]
                       for lo, hi in zip(edges[:-1], edges[1:])])
-    assert chi2_pvalue(s, edges, probs) > 1e-4
+    return chi2_pvalue(s, edges, probs)
+
+
+@pytest.mark.parametrize("T", [0.3, 2.0, 15.0])
+def test_moller_chi2(orc, T):
+    assert moller_pvalue(orc, T) > 1e-4
+
+
+# Mistakes in the Moller sampler (a mixture of the 1/eps^2, 1/(1-eps)^2 and
+# a^2 terms, kept with probability f/h) planted in a copy of the oracle: each
+# must fail the chi-square pin at one of the energies above.
+MOLLER_MUTATIONS = {
+    "second_term_dropped": ("const double w2 = 2.0 - 1.0 / (1.0 - e0);", "const double w2 = 0.0;"),
+    "interference_term_dropped": ("if (ua * h <= h - b / q) return eps;",
+                                  "if (ua * h <= h) return eps;"),
+    "third_weight_without_a2": ("const double w3 = a2 * (0.5 - e0);",
+                                "const double w3 = (0.5 - e0);"),
+    "second_inverse_unscaled": ("eps = 1.0 - 1.0 / (2.0 - ue * w2);",
+                                "eps = 1.0 - 1.0 / (2.0 - ue);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MOLLER_MUTATIONS))
+def test_moller_planted_mistake_is_caught(orc, name, tmp_path):
+    import os
+    import shutil
+    old, new = MOLLER_MUTATIONS[name]
+    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+    for f in os.listdir(src):
+        if f.endswith((".c", ".h")):
+            shutil.copy(os.path.join(src, f), tmp_path / f)
+    path = tmp_path / "transport.c"
+    text = path.read_text()
+    assert text.count(old) == 1, name
+    path.write_text(text.replace(old, new))
+    lib = orc.build(src_dir=str(tmp_path), lib_path=str(tmp_path / "liboracle_planted.so"))
+    with orc.library(lib):
+        worst = min(moller_pvalue(orc, T) for T in (0.3, 2.0, 15.0))
+    assert worst <= 1e-4, f"the Moller chi-square pin did not catch {name} (p = {worst})"
 
 
 @pytest.mark.parametrize("T", [0.5, 3.0, 15.0])
