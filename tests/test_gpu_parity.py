@@ -104,11 +104,10 @@ CASES = ["water_e15", "slab_6mv", "pair_bone", "gantry_ct", "csda", "kerma", "ra
          "halfslab_small_events64"]
 # oracle threads per case: the 256^3 grids are 134 MB per thread and batch
 ORACLE_THREADS = {"halfslab_full": 8}
-# dose tolerance (fraction of Dmax) where ten times the measured difference
-# exceeds the default of the parity rule
-DOSE_TOLS = {"slab_6mv": 1.5e-8, "slab_6mv_copies4": 1.5e-8, "slab_6mv_ordered": 1.5e-8,
-             "pair_bone": 3.5e-9,
-             "halfslab_full": 2e-5}
+# the full 256^3 half-slab: about 100 steps per track in 0.2 cm voxels spread
+# the rounding transfers over many voxels (1.8e-6 of Dmax at most, measured):
+# one bound for the whole grid, ten times that
+DOSE_RULES = {"halfslab_full": {"tol": 2e-5, "outliers": 0}}
 
 
 def dose_error(d, od):
@@ -136,7 +135,7 @@ def test_fp64_parity_counters_identical(omc, orc, W, name):
     assert ledger_residual(c) < 1e-9
     for k in ("E_incident", "E_deposited", "E_escaped"):
         assert c[k] == pytest.approx(oc[k], rel=1e-9, abs=1e-9), k
-    dose_parity(d, d2, od, od2, ph["density"], tol=DOSE_TOLS.get(name, 1e-9), tag=name)
+    dose_parity(d, d2, od, od2, ph["density"], tag=name, **DOSE_RULES.get(name, {}))
 
 
 FIXED_CASES = ["water_e15", "slab_6mv", "csda", "halfslab_small", "eight_materials", "gantry_ct"]
@@ -190,13 +189,17 @@ def test_fp64_parity_chunked_and_split(omc, orc, W):
 
 
 # Pass rule for FP32 dose against an FP64 reference (Sec. 3.1 / Table 1
-# metrics), inside the 10 % isodose of an independent third run: at least 90 %
-# of the voxels within two combined standard errors (the batch estimate has 9
-# degrees of freedom per side, so the expected coverage is about 94 %), signed
-# mean difference below 0.3 % of Dmax, and mean |dD| below 1 % of Dmax where
-# the voxel statistics allow it (combined sigma below 0.5 %).
+# metrics), inside the 10 % isodose of an independent third run: the voxels
+# within two combined standard errors (the batch estimate has 9 degrees of
+# freedom per side, so the expected coverage is about 94 %) at least 90 % of a
+# large isodose set, 80 % of one under 1000 voxels, signed mean difference below
+# 0.3 % of Dmax, and mean |dD| below 1 % of Dmax where the voxel statistics
+# allow it (combined sigma below 0.5 %). The coverage of a small set is noisy:
+# on the 15 MeV water beam (about 105 voxels, neighbours correlated along the
+# tracks) sixteen seed pairs of the FP32 build and the oracle, with either
+# Moller sampler, ranged from 0.83 to 0.98 (mean 0.92).
 def check_fp32_agreement(agr):
-    assert agr["within2s"] > 0.90
+    assert agr["within2s"] > (0.90 if agr["n"] >= 1000 else 0.80)
     assert abs(agr["bias"]) < 0.003
     if agr["sigma_rel"] < 0.005:
         assert agr["mean_abs"] < 0.01
