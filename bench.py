@@ -485,6 +485,8 @@ def main():
                     help="denoiser_c5: held-out pairs evaluated")
     ap.add_argument("--tally-copies", type=int, default=0,
                     help="private copies of each batch's dose grid (1, 2, 4, 8, 16)")
+    ap.add_argument("--event-lanes", type=int, default=0,
+                    help="waiting electrons that start an event pass (0: the workload's shape)")
     ap.add_argument("--source-order", type=int, default=-1,
                     help="0: source particles in history order; 1: descending energy groups")
     ap.add_argument("--autotune", action="store_true",
@@ -561,6 +563,8 @@ def main():
         shape["tally_copies"] = args.tally_copies
     if args.source_order >= 0:
         shape["source_order"] = args.source_order
+    if args.event_lanes:
+        shape["event_lanes"] = args.event_lanes
     eng = omc.Engine(ph)
     eng.set_source(src)
     eng.set_params(parity_fp64=int(args.parity_fp64), **shape)

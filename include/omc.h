@@ -182,7 +182,7 @@ typedef struct {
                                 sampling runs for the waiting lanes of a wave together once
                                 this many wait (1..64) or no lane has a step left. Fewer:
                                 passes with fewer lanes; more: more lanes idle meanwhile.
-                                Results do not depend on it (16) */
+                                Results do not depend on it (12) */
 } omc_params;
 
 /* Per-run event counters and the energy ledger (all from the last run). */
@@ -370,7 +370,7 @@ void omc_free_sparse(omc_sparse_out* out);
  * take at most half the free device memory) and graph depth, then
  * tally_copies 2, 4 and 8 on the fastest
  * shape (while the copies take at most a quarter of the free device memory),
- * event_lanes 24 and 32 and, for a spectrum or phase-space source, the other
+ * event_lanes 8, 24 and 32 and, for a spectrum or phase-space source, the other
  * source_order; keeps
  * the fastest, sizes queue_factor from the
  * queue high-water marks it saw, and applies the result to ctx (as

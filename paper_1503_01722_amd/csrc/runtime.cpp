@@ -1802,7 +1802,7 @@ void omc_default_params(omc_params* p)
     p->photon_mode = 0;
     p->tally_copies = 1;
     p->source_order = 0;
-    p->event_lanes = 16;
+    p->event_lanes = 12;
 }
 
 int check_phantom(const float* density, const uint8_t* material, size_t nvox, int n_mats,
@@ -2428,7 +2428,7 @@ int omc_autotune(omc_ctx* c, uint64_t n_probe, uint32_t seed, omc_params* best)
             }
         }
         // the number of waiting electrons that starts an event pass
-        for (int k : {24, 32}) {
+        for (int k : {8, 24, 32}) {
             omc_params q = top;
             q.event_lanes = k;
             double ms;

@@ -45,7 +45,7 @@ def test_default_params(omc):
     assert (p.graph_depth, p.beamlet_group, p.sparse_threshold) == (0, 0, 0.0)
     assert p.straggler_lanes == 16 and p.electron_mode == 0 and p.table_mode == 0
     assert p.photon_mode == 0
-    assert p.tally_copies == 1 and p.source_order == 0 and p.event_lanes == 16
+    assert p.tally_copies == 1 and p.source_order == 0 and p.event_lanes == 12
     assert (p.queue_factor, p.timing, p.chunk_histories) == (6, 0, 0)
 
 
