@@ -399,6 +399,14 @@ int device_tables(omc_ctx* c, DeviceTables<R>& t)
     return OMC_OK;
 }
 
+// Records a queue may hold: each of its arrays stays below 4 GiB, so that the
+// kernels address a record's fields by 32-bit byte offsets (a multiple of 64)
+template <typename R>
+constexpr uint64_t queue_records_max()
+{
+    return ((uint64_t(1) << 32) / sizeof(R) - 64) & ~uint64_t(63);
+}
+
 template <typename R>
 int ensure_queues(omc_ctx* c, DeviceQueues<R>& Q, uint32_t cap_ph, uint32_t cap_el)
 {
@@ -406,8 +414,8 @@ int ensure_queues(omc_ctx* c, DeviceQueues<R>& Q, uint32_t cap_ph, uint32_t cap_
     free_queues(Q);
     // capacities in multiples of 64 records keep every array 256-byte aligned
     // with no padding between arrays, so the layout below is exactly `bytes`
-    cap_ph = uint32_t(std::min<uint64_t>((uint64_t(cap_ph) + 63) & ~uint64_t(63), 0x7fffffc0u));
-    cap_el = uint32_t(std::min<uint64_t>((uint64_t(cap_el) + 63) & ~uint64_t(63), 0x7fffffc0u));
+    cap_ph = uint32_t(std::min<uint64_t>((uint64_t(cap_ph) + 63) & ~uint64_t(63), queue_records_max<R>()));
+    cap_el = uint32_t(std::min<uint64_t>((uint64_t(cap_el) + 63) & ~uint64_t(63), queue_records_max<R>()));
     const size_t per = 8 * sizeof(R) + 6 * sizeof(uint32_t);
     const size_t bytes = (size_t(cap_ph) * 2 + size_t(cap_el) * 2) * per;
     if (hipMalloc(&Q.mem, bytes) != hipSuccess) {
@@ -1006,7 +1014,7 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         const uint64_t cap = ((M.queue_bytes / 4) / per) & ~uint64_t(63);
         const uint64_t slack = 2 * uint64_t(tgrid) * omc::kResBlockSlots + 4096;
         const uint64_t qf = uint64_t(std::max(P.queue_factor, 1));
-        if (cap <= slack || (cap - slack) / qf < 1 || cap > 0x7fffffc0ull)
+        if (cap <= slack || (cap - slack) / qf < 1 || cap > queue_records_max<R>())
             return fail(c, OMC_EUNSUP, "the fixed scratch holds no queue for this device");
         S = std::min<uint64_t>((cap - slack) / qf, N);
         if (P.chunk_histories > 0) S = std::min<uint64_t>(S, uint64_t(P.chunk_histories));
@@ -1021,10 +1029,15 @@ int transport(omc_ctx* c, const Job& job, uint32_t seed, hipStream_t s, EventTim
         block = P.block_size;
         tgrid = c->cu_count * P.blocks_per_cu;
         // capacity: secondaries per source history, plus the holes left by the
-        // per-wave slot reservations of the two kernels that append to a queue
+        // per-wave slot reservations of the two kernels that append to a queue;
+        // a chunk too large for the largest queue is cut down to fit
         const uint64_t waves = uint64_t(tgrid) * (block / 64);
-        const uint64_t qcap = std::min<uint64_t>(
-            uint64_t(P.queue_factor) * S + 2 * waves * omc::kResBlockSlots + 4096, 0x7fffffffull);
+        const uint64_t slack = 2 * waves * omc::kResBlockSlots + 4096;
+        const uint64_t qmax = queue_records_max<R>();
+        const uint64_t qf = uint64_t(std::max(P.queue_factor, 1));
+        if (qmax <= slack + qf) return fail(c, OMC_EUNSUP, "launch shape too large for the queues");
+        S = std::min<uint64_t>(S, (qmax - slack) / qf);
+        const uint64_t qcap = qf * S + slack;
         if ((rc = ensure_queues(c, Q, uint32_t(std::max<uint64_t>(qcap, S)), uint32_t(qcap))))
             return rc;
         for (int k = 0; k < 4; ++k) Qv[k] = Q.q[k];
