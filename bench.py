@@ -37,7 +37,8 @@ sys.path.insert(0, ROOT)
 
 # Nominal algorithmic work per event in VALU lane operations (an add, mul, FMA,
 # compare or integer op counts 1, a transcendental 4, a Philox block 100, a
-# uniform 27 including its share of a block). Frozen; see the design doc.
+# uniform 27 including its share of a block). Frozen: the work the algorithm needs,
+# not the instructions the compiler issues.
 OPS = {
     "photon": {"ph_flights": 154, "ph_compton": 362, "ph_photo": 10, "ph_pair": 120},
     "electron": {"el_steps": 380, "el_hard_cand": 114, "el_moller": 230, "el_brems": 230,
@@ -510,8 +511,9 @@ def main():
                           "check": float(y[-1].item())}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the history-range sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the engine runs on one GPU per process; several GPUs "
+              "would take disjoint history ranges and sum the dose grids, which is not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
