@@ -27,14 +27,28 @@ def kn_dcs(E, c):
     return 0.5 * RE**2 * r * r * (r + 1.0 / r - (1.0 - c * c))
 
 
+def compton_pvalue(orc, E, n=200_000):
+    """chi-square p-value of the oracle's Compton scattering angles against the
+    Klein-Nishina cross section integrated by quadrature; 0 if a sample breaks
+    the Compton kinematics or leaves [eps0, 1]."""
+    eps, cost, words = orc.sample_compton(E, n, seed=11)
+    k = E / MC2
+    if not (np.allclose(eps, 1.0 / (1.0 + k * (1.0 - cost)), rtol=1e-12)
+            and np.all(eps >= 1.0 / (1.0 + 2.0 * k) - 1e-15) and np.all(eps <= 1.0)):
+        return 0.0
+    edges = np.linspace(-1, 1, 41)
+    probs = np.array([integrate.quad(lambda c: kn_dcs(E, c), a, b, epsabs=0, epsrel=1e-10)[0]
+                      for a, b in zip(edges[:-1], edges[1:])])
+    return chi2_pvalue(cost, edges, probs)
+
+
 @pytest.mark.parametrize("E", [0.05, 0.5, 5.0])
 def test_compton_angle_chi2(orc, E):
     n = 200_000
     eps, cost, words = orc.sample_compton(E, n, seed=11)
-    edges = np.linspace(-1, 1, 41)
-    probs = np.array([integrate.quad(lambda c: kn_dcs(E, c), a, b, epsabs=0, epsrel=1e-10)[0]
-                      for a, b in zip(edges[:-1], edges[1:])])
-    assert chi2_pvalue(cost, edges, probs) > 1e-4
+    assert compton_pvalue(orc, E, n) > 1e-4
+    # three uniforms per rejection round
+    assert np.all(words % 3 == 0) and words.min() == 3
     # Compton kinematics: E'/E = 1/(1 + k(1 - cos))
     k = E / MC2
     assert np.allclose(eps, 1.0 / (1.0 + k * (1.0 - cost)), rtol=1e-12)
@@ -101,15 +115,64 @@ def test_moller_planted_mistake_is_caught(orc, name, tmp_path):
     assert worst <= 1e-4, f"the Moller chi-square pin did not catch {name} (p = {worst})"
 
 
-@pytest.mark.parametrize("T", [0.5, 3.0, 15.0])
-def test_brems_chi2(orc, T):
+def brems_pvalue(orc, T, n=200_000):
+    """chi-square p-value of the oracle's bremsstrahlung photon energies against
+    the (1/k)(4/3 - 4/3 y + y^2) spectrum on [kc, T] (its closed-form CDF); 0 if
+    a sample leaves [kc, T]."""
     kc = 0.2
     cdf = lambda k: 4 / 3 * np.log(k / kc) - 4 / 3 * (k - kc) / T + (k * k - kc * kc) / (2 * T * T)
-    s = orc.sample_brems(T, kc, 200_000, seed=9)
-    assert s.min() >= kc and s.max() <= T
+    s = orc.sample_brems(T, kc, n, seed=9)
+    if s.min() < kc or s.max() > T:
+        return 0.0
     edges = np.geomspace(kc, T, 41)
-    probs = np.diff(cdf(edges))
-    assert chi2_pvalue(s, edges, probs) > 1e-4
+    return chi2_pvalue(s, edges, np.diff(cdf(edges)))
+
+
+@pytest.mark.parametrize("T", [0.5, 3.0, 15.0])
+def test_brems_chi2(orc, T):
+    assert brems_pvalue(orc, T) > 1e-4
+
+
+# Mistakes in the Klein-Nishina (Butcher-Messel) and bremsstrahlung samplers
+# planted in a copy of the oracle: each must fail its chi-square pin at one
+# of the energies above.
+SAMPLER_MUTATIONS = {
+    "compton_branch_weights_swapped": (
+        "compton", "if (ua * (a1 + a2) < a1) eps = exp(-a1 * ub);",
+        "if (ua * (a1 + a2) < a2) eps = exp(-a1 * ub);"),
+    "compton_rejection_without_eps": (
+        "compton", "if (uc <= 1.0 - eps * sin2 / (1.0 + eps * eps)) {",
+        "if (uc <= 1.0 - sin2 / (1.0 + eps * eps)) {"),
+    "compton_second_branch_linear": (
+        "compton", "else eps = sqrt(e0 * e0 + (1.0 - e0 * e0) * ub);",
+        "else eps = e0 + (1.0 - e0) * ub;"),
+    "brems_rejection_without_quadratic": (
+        "brems", "if (ub <= 1.0 - y + 0.75 * y * y) return k;", "if (ub <= 1.0 - y) return k;"),
+    "brems_envelope_linear": (
+        "brems", "const double k = kc * exp(ua * lr);", "const double k = kc + ua * (T - kc);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SAMPLER_MUTATIONS))
+def test_sampler_planted_mistake_is_caught(orc, name, tmp_path):
+    import os
+    import shutil
+    which, old, new = SAMPLER_MUTATIONS[name]
+    src = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+    for f in os.listdir(src):
+        if f.endswith((".c", ".h")):
+            shutil.copy(os.path.join(src, f), tmp_path / f)
+    path = tmp_path / "transport.c"
+    text = path.read_text()
+    assert text.count(old) == 1, name
+    path.write_text(text.replace(old, new))
+    lib = orc.build(src_dir=str(tmp_path), lib_path=str(tmp_path / "liboracle_planted.so"))
+    with orc.library(lib):
+        if which == "compton":
+            worst = min(compton_pvalue(orc, E) for E in (0.05, 0.5, 5.0))
+        else:
+            worst = min(brems_pvalue(orc, T) for T in (0.5, 3.0, 15.0))
+    assert worst <= 1e-4, f"the {which} chi-square pin did not catch {name} (p = {worst})"
 
 
 @pytest.mark.parametrize("x", [1e-4, 0.05, 0.7, 4.0])
