@@ -22,6 +22,10 @@ CASES = {
     "compton_low": [0.08, *DIR0],
     "moller": [3.0, *DIR0],
     "moller_thresh": [0.12, *DIR0],
+    # the mixture's first term dominates at 15 MeV; its other two terms and
+    # the interference term matter at 0.3 MeV
+    "moller_high": [15.0, *DIR0],
+    "moller_low": [0.3, *DIR0],
     "brems": [5.0, *DIR0],
     # the deflection depends on s / lambda_1 only; the energy is not used
     "ms": [1.0, *DIR0, 0.3],
